@@ -1,0 +1,190 @@
+/*
+ * lks.h - C ABI of the MI355X (gfx950) library for the moving-body lattice kinetic scheme (LKS),
+ * its rigid-body design-to-analysis transfer and its exact discrete adjoint.
+ *
+ * Method: Tanabe, Yaji, Ushijima, "Topology optimization of actively moving rigid bodies in
+ * unsteady flows" (arXiv 2506.23895).
+ *   - problem statement: Eq. (1), min_gamma J(gamma, p, u), 0 <= gamma <= 1 (Sec. 2.1);
+ *   - velocity sets D2Q9 / D3Q15 (Sec. 2.2, Fig. of the velocity sets) and D3Q19;
+ *   - LKS update with tau = 1: pull of the equilibrium (Eqs. rho and u), equilibrium with the
+ *     viscous A-term, nu = (1/6 - 2A/9) dx (Sec. 2.2);
+ *   - Brinkman interpolation kappa_ref(gamma) (Sec. 2.3, first equation);
+ *   - rigid motion of the design grid (Eqs. rigid_body_position, rigid_body_velocity);
+ *   - transfer of kappa and the solid velocity with W = prod w (Eqs. brinkman_ref,
+ *     velocity_ref and the weight functions); implicit VPM update (Eq. u_ex_2);
+ *   - macroscopic boundary conditions (Eqs. bc_rho, bc_u);
+ *   - Algorithm 1 (forward) and Algorithm 2 (reverse), design sensitivity pulled back to the
+ *     design grid (Sec. 2.4); objectives J1, J2 over a window I (Sec. 2.5).
+ * The reverse sweep is the exact derivative of the discrete forward map (the transposes of the
+ * pull, equilibrium, force update, boundary conditions and transfer), which has the structure
+ * of the paper's ALKS: a pull from x + c_i, w-weighted moments rho~, u~, s~ and the adjoint
+ * equilibrium.
+ *
+ * Units: lattice units (dx = dt = 1).  The design grid has unit spacing; design node (i,j,k)
+ * sits at xi = (i,j,k) in the design frame.  Analysis node (i,j,k) sits at x = (i,j,k).
+ *
+ * Conventions for every entry point:
+ *   - return int: LKS_OK (0) or a negative LKS_E* code; no C++ exception crosses the ABI;
+ *   - the caller owns every input and output buffer; the library copies what it keeps and never
+ *     holds a caller pointer after a call returns;
+ *   - a context owns all the device memory it allocates; contexts are independent; one context
+ *     must not be used from two threads at once;
+ *   - all GPU work of a context is enqueued on its stream; entry points that return results to
+ *     the host synchronise that stream before returning;
+ *   - lks_last_error(ctx) describes the last failure on that context.
+ */
+#ifndef LKS_H
+#define LKS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes --------------------------------------------------------------------- */
+#define LKS_OK 0
+#define LKS_EINVAL (-1)        /* malformed descriptor or argument                        */
+#define LKS_ENOMEM (-2)        /* over the HBM budget, or a device allocation failed       */
+#define LKS_ESTATE (-3)        /* call out of order (adjoint before forward, ...)         */
+#define LKS_ENONFINITE (-4)    /* a NaN/Inf appeared in the state                         */
+#define LKS_EDEVICE (-5)       /* a HIP runtime call failed                               */
+#define LKS_EUNSUPPORTED (-6)  /* valid but not supported by this build                   */
+
+/* ---- enumerations ----------------------------------------------------------------------- */
+enum { LKS_D2Q9 = 0, LKS_D3Q15 = 1, LKS_D3Q19 = 2 };
+/* Brinkman interpolation.  PAPER: gamma = 1 solid, kappa_ref = kmax q g / ((1 - g) + q).
+ * FLUID_ONE: gamma = 1 fluid, kappa_ref = kmax q (1 - g) / (q + g) (the mirror form). */
+enum { LKS_INTERP_PAPER = 0, LKS_INTERP_FLUID_ONE = 1 };
+/* transfer kernel w: COS4 = (1 + cos(pi r/2))/4 on |r| <= 2 (Peskin); LIN = max(0, 1 - |r|) */
+enum { LKS_W_COS4 = 0, LKS_W_LIN = 1 };
+/* boundary kinds, applied face by face in the order x-, x+, y-, y+, z-, z+ (a later face wins
+ * at shared edges).  With s the next node inward from a face node:
+ *   VELOCITY / NOSLIP : u = u_bar, rho = rho(s)
+ *   ZERO_GRADIENT     : rho = rho(s), u = u(s)
+ *   PRESSURE          : rho = rho_bar, normal u = normal u(s), tangential u = u_bar
+ *   PERIODIC          : both faces of the axis must be PERIODIC */
+enum { LKS_BC_PERIODIC = 0, LKS_BC_VELOCITY = 1, LKS_BC_PRESSURE = 2, LKS_BC_ZERO_GRADIENT = 3,
+       LKS_BC_NOSLIP = 4 };
+/* objective densities summed over the mask and over steps n0..n1 (Sec. 2.5 for J1, J2; the
+ * body-force kinds use F_b = kappa (u - u_S), the reaction of the VPM force on the fluid):
+ *   POWER  : F_b . u_S          DRAG : F_b . dir          TORQUE : dir . ((x - centre) x F_b)
+ *   J1     : -rho / 3           J2   : -dir . u           MASS   : rho          NONE : no J */
+enum { LKS_OBJ_NONE = -1, LKS_OBJ_POWER = 0, LKS_OBJ_DRAG = 1, LKS_OBJ_TORQUE = 2,
+       LKS_OBJ_J1 = 3, LKS_OBJ_J2 = 4, LKS_OBJ_MASS = 5 };
+#define LKS_NORM_TIME 1 /* divide J by (n1 - n0 + 1)  */
+#define LKS_NORM_MASK 2 /* divide J by the mask count */
+enum { LKS_F32 = 0, LKS_F64 = 1 };
+#define LKS_STATE_FINAL (-1)
+
+/* ---- descriptor ------------------------------------------------------------------------- */
+typedef struct {
+    int kind;       /* LKS_BC_* */
+    double rho;     /* rho_bar (PRESSURE) */
+    double u[3];    /* u_bar (VELOCITY, NOSLIP; tangential part for PRESSURE) */
+} lks_bc;
+
+/* rigid motion at step n (record n is used at t_n = n):
+ *   x_ref(xi) = R (xi - xi_G) + xG,   u_ref(xi) = omega x (R (xi - xi_G)) + uG
+ * R row-major and orthogonal; in 2D R must be a rotation about z and omega = (0, 0, w). */
+typedef struct {
+    double R[9];
+    double omega[3];
+    double xG[3];
+    double uG[3];
+} lks_motion;
+
+typedef struct {
+    int kind;            /* LKS_OBJ_* */
+    int n0, n1;          /* window, 1 <= n0 <= n1 <= nsteps */
+    int normalize;       /* LKS_NORM_* bits */
+    double centre[3];    /* TORQUE reference point */
+    double dir[3];       /* DRAG / J2 direction, TORQUE axis */
+    const uint8_t *mask; /* host [ncell] (x fastest) or NULL = every node; copied */
+} lks_objective;
+
+typedef struct {
+    int dim;                     /* 2 or 3 */
+    int lattice;                 /* LKS_D2Q9 (dim 2), LKS_D3Q15 / LKS_D3Q19 (dim 3) */
+    int n[3];                    /* analysis grid; n[2] = 1 in 2D; >= 4 on non-periodic axes,
+                                    >= 3 on periodic ones */
+    int nd[3];                   /* design grid; nd[2] = 1 in 2D */
+    double xi_G[3];              /* design-frame point mapped to xG */
+    double nu;                   /* kinematic viscosity (> 0); A = 4.5 (1/6 - nu) */
+    int interp;                  /* LKS_INTERP_* */
+    double kappa_max, q;         /* Brinkman interpolation parameters */
+    int weight;                  /* LKS_W_* */
+    lks_bc bc[6];                /* faces x-, x+, y-, y+, z-, z+ (z ignored in 2D) */
+    double rho0, u0[3];          /* uniform initial state ... */
+    const double *rho_init;      /* ... or host [ncell] (optional, copied) */
+    const double *u_init;        /* ... host [3*ncell] component-major (optional, copied) */
+    const double *kappa_static;  /* host [ncell] static Brinkman field, zero velocity (optional) */
+    double body_force[3];        /* uniform force added to u* (test use; usually 0) */
+    int nsteps;                  /* N >= 1 */
+    const lks_motion *motion;    /* host, nsteps + 1 records (copied) */
+    lks_objective objective;
+    int precision;               /* LKS_F32 or LKS_F64 */
+    int checkpoint_every;        /* K: state checkpoints every K steps and recomputation of each
+                                    segment in reverse; 0 keeps the whole trajectory */
+    int io_on_device;            /* gamma, dJdgamma and read_state buffers are device pointers */
+    void *stream;                /* hipStream_t, or NULL for the null stream */
+    size_t hbm_budget_bytes;     /* 0 = no budget; else lks_create fails with LKS_ENOMEM above it */
+} lks_desc;
+
+typedef struct lks_ctx lks_ctx;
+
+/* Device bytes a context for *d would allocate (the HBM ledger).  Validates *d; no GPU call. */
+int lks_query_bytes(const lks_desc *d, size_t *bytes);
+
+/* Validate *d, copy what it points to and allocate every device buffer.  The rigid-body
+ * footprint (mapped design grid plus the kernel support) must stay inside the domain at every
+ * step, at least one node away from every non-periodic face, and must not wrap a periodic axis
+ * (LKS_EINVAL otherwise).  *out is NULL on failure. */
+int lks_create(const lks_desc *d, lks_ctx **out);
+
+/* Free the context (NULL is a no-op).  Synchronises its stream. */
+void lks_destroy(lks_ctx *c);
+
+/* Algorithm 1: kappa_ref = I(gamma) on the design grid, then for n = 1..N the transfer of kappa
+ * and u_S at t_n, the LKS pull, the VPM force update and the boundary conditions, with the
+ * objective accumulated in FP64 over the window.  gamma: [nd] in the context precision (float or
+ * double), host or device memory per io_on_device, read before return.  *J receives the
+ * objective (host).  Replaces any previous trajectory.  LKS_ENONFINITE if the final state holds
+ * a NaN/Inf. */
+int lks_forward(lks_ctx *c, const void *gamma, double *J);
+
+/* Algorithm 2: the exact reverse sweep against the last forward, restoring each checkpointed
+ * segment and recomputing it before its reverse steps, accumulating G(xi) = sum_n sum_x
+ * W_n(x, xi) kappa_bar^n(x) in FP64.  LKS_ESTATE if no forward has run. */
+int lks_adjoint(lks_ctx *c);
+
+/* dJ/dgamma = I'(gamma) * G on the design grid, [nd] in the context precision, host or device
+ * per io_on_device.  LKS_ESTATE if no adjoint has run since the last forward. */
+int lks_sensitivity(lks_ctx *c, void *dJdgamma);
+
+/* Copy a state of the last forward: which = LKS_STATE_FINAL for X^N, or k >= 0 for the state
+ * at step k * checkpoint_every (k = 0 is the initial state).  drho = rho - 1 as [ncell] and
+ * u as [dim][ncell] (component-major), context precision, host or device per io_on_device;
+ * either pointer may be NULL.  LKS_ESTATE before a forward, LKS_EINVAL for an unknown k. */
+int lks_read_state(lks_ctx *c, int which, void *drho, void *u);
+
+/* Per-step objective values j^n (n = 0..nsteps, already scaled), host double[nsteps + 1]. */
+int lks_read_objective_steps(lks_ctx *c, double *jn);
+
+/* Kernel timing: sample every k-th launch of each kernel kind with HIP events on the context
+ * stream (k = 0 switches sampling off).  lks_kernel_timing returns, for kind 0 = forward step,
+ * 1 = adjoint step, 2 = sensitivity gather, the number of sampled launches and their mean
+ * duration in milliseconds. */
+int lks_set_timing(lks_ctx *c, int every);
+int lks_kernel_timing(lks_ctx *c, int kind, long *count, double *mean_ms);
+
+/* Static description of the last failure of c (or of the last failed lks_create when c is
+ * NULL), and of a return code. */
+const char *lks_last_error(const lks_ctx *c);
+const char *lks_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LKS_H */

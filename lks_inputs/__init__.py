@@ -175,11 +175,12 @@ def config_c1(precision: str = "F64") -> dict:
                        u0=(U_IN, 0, 0), precision=precision)
 
 
-def config_c2(precision: str = "F32", nsteps: int = 20000) -> dict:
-    """2048x1024 channel, 512^2 design under heave A=64 + pitch 0.5 sin(wt), w=2pi/2000, forward only."""
+def config_c2(precision: str = "F32", nsteps: int = 20000, period: float = 2000.0) -> dict:
+    """2048x1024 channel, 512^2 design under heave A=64 + pitch 0.5 sin(wt), w = 2pi/period
+    (stated 2pi/2000), forward only."""
     n, nd = (2048, 1024), (512, 512)
     centre = ((n[0] - 1) / 2.0, (n[1] - 1) / 2.0, 0.0)
-    w = 2 * math.pi / 2000
+    w = 2 * math.pi / period
     mot = motion_heave(nsteps, centre, 64.0, w, theta_amp=0.5)
     return make_config(name="c2_2d_2048x1024_fwd", dim=2, lattice="D2Q9", n=n, nd=nd,
                        nu=nu_from_re(200, U_IN, nd[0]), nsteps=nsteps, motion=mot,
@@ -188,11 +189,13 @@ def config_c2(precision: str = "F32", nsteps: int = 20000) -> dict:
 
 
 def config_c3(n_side: int = 1024, nd_side: int = 256, precision: str = "F32",
-              nsteps: int = 10000, checkpoint_every: int = 100, seed: int = 2) -> dict:
-    """D2Q9 channel rotating design (w=2pi/1000), time-averaged drag, checkpoint every 100 steps."""
+              nsteps: int = 10000, checkpoint_every: int = 100, seed: int = 2,
+              period: float = 1000.0) -> dict:
+    """D2Q9 channel, rotating design (w = 2pi/period, stated 2pi/1000), time-averaged drag,
+    checkpoint every 100 steps."""
     n, nd = (n_side, n_side), (nd_side, nd_side)
     centre = ((n[0] - 1) / 2.0, (n[1] - 1) / 2.0, 0.0)
-    mot = motion_rotation(nsteps, centre, 2 * math.pi / 1000)
+    mot = motion_rotation(nsteps, centre, 2 * math.pi / period)
     return make_config(name=f"c3_2d_{n_side}_fwdadj", dim=2, lattice="D2Q9", n=n, nd=nd,
                        nu=nu_from_re(100, U_IN, 256), nsteps=nsteps, motion=mot,
                        bcs=channel_bcs(2, U_IN), obj=objective("DRAG", 1, nsteps, norm=1),

@@ -17,6 +17,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #ifndef M_PI
 #define M_PI 3.14159265358979323846
@@ -761,4 +764,13 @@ int or_solve(const or_desc *d, const double *gamma, double *J, double *jn, doubl
 done:
     free(kref); free(kpr); free(kappa); free(uS); free(rho_t); free(u_t);
     return rc;
+}
+
+/* threads the OpenMP loops of this library use (1 without OpenMP) */
+int or_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

@@ -114,6 +114,9 @@ int or_objective_partials(const or_desc *d, const double *kappa, const double *u
 int or_solve(const or_desc *d, const double *gamma, double *J, double *jn, double *grad,
              double *rho_final, double *u_final, double *rho_traj, double *u_traj);
 
+/* threads used by the OpenMP loops */
+int or_num_threads(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -73,6 +73,7 @@ def lib():
         L.or_objective_step.restype = C.c_double
         L.or_objective_partials.argtypes = [P, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
         L.or_solve.argtypes = [P, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.or_num_threads.restype = C.c_int
         _lib = L
     return _lib
 
@@ -245,3 +246,7 @@ def solve(cfg: dict, gamma: np.ndarray, grad: bool = True, traj: bool = False) -
     if rc:
         raise ValueError(f"oracle solve failed: {rc}")
     return {"J": J.value, "jn": jn, "grad": gr, "rho": rho, "u": u, "rho_traj": rt, "u_traj": ut}
+
+
+def num_threads() -> int:
+    return int(lib().or_num_threads())

@@ -1,0 +1,850 @@
+// Host runtime of the LKS library: descriptor validation, the HBM ledger, device buffers, and
+// the drivers of Algorithm 1 (forward with state checkpoints every K steps) and of the reverse
+// sweep (restore a checkpoint, recompute its segment into the trajectory store, then run the
+// adjoint step and the sensitivity gather for each step of the segment, last step first).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lks.h"
+#include "lks_internal.hpp"
+
+using lks::BoxGeom;
+using lks::Geom;
+using lks::StepMotion;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+const char *kind_name(int k) {
+    switch (k) {
+    case 0: return "forward step";
+    case 1: return "adjoint step";
+    case 2: return "sensitivity gather";
+    }
+    return "?";
+}
+
+struct Layout {
+    Geom g{};
+    long long pitch = 0;     // padded row length (elements)
+    long long F = 0;         // elements per field
+    long long ncell = 0;
+    long long nd = 0;
+    int K = 0;               // segment length
+    int S = 0;               // number of segments (= checkpoints)
+    size_t esz = 0;
+    BoxGeom box{};
+    std::vector<StepMotion> steps;  // index n = 0..N
+    size_t bytes = 0;
+    // byte sizes of each allocation
+    size_t b_state = 0, b_ckpt = 0, b_traj = 0, b_box = 0, b_kbar = 0, b_adj = 0, b_design = 0,
+           b_aux = 0, b_final = 0;
+    long long max_blocks = 0;
+    bool fwd_only = false;   // objective NONE: forward sweep only, no trajectory or adjoint storage
+};
+
+int fail(std::string *err, int code, const std::string &msg) {
+    if (err) *err = msg;
+    return code;
+}
+
+bool finite3(const double *v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+// Validate the descriptor and compute every size the context needs (no GPU call).
+int plan(const lks_desc *d, Layout &L, std::string *err) {
+    if (!d) return fail(err, LKS_EINVAL, "descriptor is NULL");
+    if (d->dim != 2 && d->dim != 3) return fail(err, LKS_EINVAL, "dim must be 2 or 3");
+    const int D = d->dim;
+    if (D == 2 && d->lattice != LKS_D2Q9) return fail(err, LKS_EINVAL, "2D needs LKS_D2Q9");
+    if (D == 3 && d->lattice != LKS_D3Q15 && d->lattice != LKS_D3Q19)
+        return fail(err, LKS_EINVAL, "3D needs LKS_D3Q15 or LKS_D3Q19");
+    if (d->precision != LKS_F32 && d->precision != LKS_F64)
+        return fail(err, LKS_EINVAL, "precision must be LKS_F32 or LKS_F64");
+    if (d->interp != LKS_INTERP_PAPER && d->interp != LKS_INTERP_FLUID_ONE)
+        return fail(err, LKS_EINVAL, "unknown interpolation");
+    if (d->weight != LKS_W_COS4 && d->weight != LKS_W_LIN)
+        return fail(err, LKS_EINVAL, "unknown transfer weight");
+    if (!(d->nu > 0.0) || !std::isfinite(d->nu)) return fail(err, LKS_EINVAL, "nu must be > 0");
+    if (!(d->q > 0.0) || !std::isfinite(d->q) || !std::isfinite(d->kappa_max) || d->kappa_max < 0)
+        return fail(err, LKS_EINVAL, "need q > 0 and kappa_max >= 0");
+    if (d->nsteps < 1) return fail(err, LKS_EINVAL, "nsteps must be >= 1");
+    if (!d->motion) return fail(err, LKS_EINVAL, "motion table is NULL");
+    if (d->checkpoint_every < 0) return fail(err, LKS_EINVAL, "checkpoint_every must be >= 0");
+    if (!std::isfinite(d->rho0) || !finite3(d->u0) || !finite3(d->body_force) || !finite3(d->xi_G))
+        return fail(err, LKS_EINVAL, "non-finite initial state, force or xi_G");
+
+    Geom &g = L.g;
+    g.dim = D;
+    for (int a = 0; a < 3; ++a) {
+        if (a >= D) {
+            if (d->n[a] != 1 || d->nd[a] != 1) return fail(err, LKS_EINVAL, "2D needs n[2] = nd[2] = 1");
+            g.n[a] = 1;
+            g.per[a] = 1;
+            continue;
+        }
+        const int km = d->bc[2 * a].kind, kp = d->bc[2 * a + 1].kind;
+        for (int k : {km, kp})
+            if (k < LKS_BC_PERIODIC || k > LKS_BC_NOSLIP) return fail(err, LKS_EINVAL, "unknown boundary kind");
+        if ((km == LKS_BC_PERIODIC) != (kp == LKS_BC_PERIODIC))
+            return fail(err, LKS_EINVAL, "both faces of a periodic axis must be PERIODIC");
+        g.per[a] = km == LKS_BC_PERIODIC;
+        if (d->n[a] < (g.per[a] ? 3 : 4))
+            return fail(err, LKS_EINVAL, "n must be >= 4 on non-periodic axes and >= 3 on periodic ones");
+        if (d->n[a] > (1 << 20) || d->nd[a] < 1 || d->nd[a] > (1 << 20))
+            return fail(err, LKS_EINVAL, "grid extent out of range");
+        g.n[a] = d->n[a];
+        for (int s = 0; s < 2; ++s)
+            if (!std::isfinite(d->bc[2 * a + s].rho) || !finite3(d->bc[2 * a + s].u))
+                return fail(err, LKS_EINVAL, "non-finite boundary value");
+    }
+    const lks_objective &ob = d->objective;
+    if (ob.kind != LKS_OBJ_NONE) {
+        if (ob.kind < LKS_OBJ_POWER || ob.kind > LKS_OBJ_MASS) return fail(err, LKS_EINVAL, "unknown objective");
+        if (ob.n0 < 1 || ob.n1 > d->nsteps || ob.n0 > ob.n1)
+            return fail(err, LKS_EINVAL, "objective window must satisfy 1 <= n0 <= n1 <= nsteps");
+        if (!finite3(ob.centre) || !finite3(ob.dir)) return fail(err, LKS_EINVAL, "non-finite objective vector");
+    }
+
+    L.pitch = ((g.n[0] + 63) / 64) * 64;
+    g.sy = L.pitch;
+    g.sz = L.pitch * g.n[1];
+    L.F = g.sz * g.n[2];
+    L.ncell = (long long)g.n[0] * g.n[1] * g.n[2];
+    L.nd = (long long)d->nd[0] * d->nd[1] * d->nd[2];
+    L.esz = d->precision == LKS_F64 ? 8 : 4;
+    const int N = d->nsteps;
+    L.fwd_only = d->objective.kind == LKS_OBJ_NONE;  // nothing to differentiate: no reverse buffers
+    L.K = (L.fwd_only || d->checkpoint_every == 0 || d->checkpoint_every >= N) ? N : d->checkpoint_every;
+    L.S = (N + L.K - 1) / L.K;
+
+    // rigid motion: orthogonal R; 2D motion stays in the plane; footprint inside the domain
+    const double s = d->weight == LKS_W_LIN ? 1.0 : 2.0;
+    L.steps.resize(N + 1);
+    int bn[3] = {1, 1, 1};
+    for (int n = 0; n <= N; ++n) {
+        const lks_motion &m = d->motion[n];
+        for (int i = 0; i < 9; ++i)
+            if (!std::isfinite(m.R[i])) return fail(err, LKS_EINVAL, "non-finite rotation");
+        if (!finite3(m.omega) || !finite3(m.xG) || !finite3(m.uG))
+            return fail(err, LKS_EINVAL, "non-finite motion record");
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double v = 0;
+                for (int k = 0; k < 3; ++k) v += m.R[3 * i + k] * m.R[3 * j + k];
+                if (std::fabs(v - (i == j ? 1.0 : 0.0)) > 1e-9)
+                    return fail(err, LKS_EINVAL, "motion R is not orthogonal at step " + std::to_string(n));
+            }
+        if (D == 2 && (m.R[2] != 0 || m.R[5] != 0 || m.R[6] != 0 || m.R[7] != 0 || m.R[8] != 1 ||
+                       m.omega[0] != 0 || m.omega[1] != 0 || m.uG[2] != 0))
+            return fail(err, LKS_EINVAL, "2D motion must rotate about z and stay in the plane");
+        StepMotion &sm = L.steps[n];
+        std::memcpy(sm.R, m.R, sizeof sm.R);
+        std::memcpy(sm.Om, m.omega, sizeof sm.Om);
+        std::memcpy(sm.xG, m.xG, sizeof sm.xG);
+        std::memcpy(sm.uG, m.uG, sizeof sm.uG);
+        if (D == 2) sm.xG[2] = 0.0;
+        double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+        for (int c = 0; c < (1 << D); ++c) {
+            double xi[3] = {0, 0, 0};
+            for (int a = 0; a < D; ++a) xi[a] = ((c >> a) & 1) ? d->nd[a] - 1 : 0;
+            for (int r = 0; r < D; ++r) {
+                double v = sm.xG[r];
+                for (int a = 0; a < D; ++a) v += sm.R[3 * r + a] * (xi[a] - d->xi_G[a]);
+                mn[r] = std::min(mn[r], v);
+                mx[r] = std::max(mx[r], v);
+            }
+        }
+        for (int a = 0; a < 3; ++a) {
+            if (a >= D) {
+                sm.lo[a] = sm.hi[a] = 0;
+                continue;
+            }
+            // nodes with a non-zero weight lie strictly inside (min - s, max + s)
+            sm.lo[a] = (int)std::floor(mn[a] - s) + 1;
+            sm.hi[a] = (int)std::ceil(mx[a] + s) - 1;
+            const int lim_lo = g.per[a] ? 0 : 1, lim_hi = g.per[a] ? g.n[a] - 1 : g.n[a] - 2;
+            if (n >= 1 && (sm.lo[a] < lim_lo || sm.hi[a] > lim_hi))
+                return fail(err, LKS_EINVAL,
+                            "rigid-body footprint leaves the interior at step " + std::to_string(n));
+            sm.lo[a] = std::max(sm.lo[a], lim_lo);
+            sm.hi[a] = std::min(sm.hi[a], lim_hi);
+            bn[a] = std::max(bn[a], sm.hi[a] - sm.lo[a] + 1);
+        }
+    }
+    L.box.bn[0] = bn[0];
+    L.box.bn[1] = bn[1];
+    L.box.bn[2] = bn[2];
+    L.box.bsy = bn[0];
+    L.box.bsz = (long long)bn[0] * bn[1];
+    L.box.cells = (long long)bn[0] * bn[1] * bn[2];
+
+    const size_t e = L.esz;
+    const size_t nf = 1 + D;
+    L.b_state = 2 * nf * L.F * e;
+    L.b_ckpt = (size_t)L.S * nf * L.F * e;
+    L.b_traj = L.fwd_only ? 0 : (size_t)(L.K + 1) * D * L.F * e;
+    L.b_box = L.fwd_only ? 0 : (size_t)L.K * nf * L.box.cells * e;
+    L.b_kbar = L.fwd_only ? 0 : (size_t)L.box.cells * e;
+    L.b_adj = L.fwd_only ? 0 : 2 * nf * L.F * e;
+    L.b_final = nf * L.F * e;
+    L.b_design = (size_t)L.nd * (3 * e + 2 * 8);  // gamma, kref, sens out; kprime, G
+    L.max_blocks = std::max(lks::fwd_blocks(g, d->lattice), lks::adj_blocks(g, d->lattice));
+    // objective partials: one row of per-block sums per step of the window, reduced at the end
+    const long long obj_rows = d->objective.kind == LKS_OBJ_NONE ? 1 : (d->objective.n1 - d->objective.n0 + 1);
+    L.b_aux = (size_t)(d->nsteps + 1) * 8 + (size_t)obj_rows * L.max_blocks * 8 + 64;
+    if (d->kappa_static) L.b_aux += L.F * e;
+    if (d->objective.kind != LKS_OBJ_NONE && d->objective.mask) L.b_aux += L.F;
+    if (d->rho_init || d->u_init) L.b_aux += nf * L.F * e;
+    L.bytes = L.b_state + L.b_ckpt + L.b_traj + L.b_box + L.b_kbar + L.b_adj + L.b_final +
+              L.b_design + L.b_aux;
+    if (d->hbm_budget_bytes && L.bytes > d->hbm_budget_bytes)
+        return fail(err, LKS_ENOMEM, "context needs " + std::to_string(L.bytes) +
+                                          " bytes, over the HBM budget");
+    return LKS_OK;
+}
+
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    int kind = 0;
+};
+
+}  // namespace
+
+struct lks_ctx {
+    lks_desc d{};
+    Layout L;
+    std::vector<lks_motion> motion;
+    hipStream_t stream = nullptr;
+    int dev = 0;
+    // device memory
+    char *state = nullptr, *ckpt = nullptr, *traj = nullptr, *box = nullptr, *kbar = nullptr,
+         *adj = nullptr, *fin = nullptr, *gamma = nullptr, *kref = nullptr, *sens = nullptr,
+         *kstatic = nullptr, *init = nullptr;
+    double *kprime = nullptr, *G = nullptr, *jn = nullptr, *partials = nullptr;
+    unsigned int *counter = nullptr;
+    int *flag = nullptr;
+    uint8_t *mask = nullptr;
+    std::vector<void *> allocs;
+    double obj_scale = 0.0;
+    bool have_fwd = false, have_adj = false;
+    std::string err;
+    // timing
+    int every = 0;
+    long launches[3] = {0, 0, 0};
+    long samples[3] = {0, 0, 0};
+    double total_ms[3] = {0, 0, 0};
+    std::vector<EventPair> pool;
+    size_t pool_used = 0;
+
+    size_t esz() const { return L.esz; }
+    int D() const { return d.dim; }
+    char *field(char *base, long long slot_fields) const { return base + slot_fields * L.F * L.esz; }
+};
+
+namespace {
+
+#define HIPCHK(ctx, expr)                                                                   \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess) {                                                             \
+            (ctx)->err = std::string(#expr) + ": " + hipGetErrorString(e_);                 \
+            return LKS_EDEVICE;                                                             \
+        }                                                                                   \
+    } while (0)
+
+int dalloc(lks_ctx *c, size_t bytes, void **p) {
+    if (bytes == 0) {
+        *p = nullptr;
+        return LKS_OK;
+    }
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        c->err = std::string("hipMalloc failed: ") + hipGetErrorString(e);
+        *p = nullptr;
+        return LKS_ENOMEM;
+    }
+    c->allocs.push_back(*p);
+    return LKS_OK;
+}
+
+template <typename T>
+lks::BCParams<T> bc_params(const lks_desc &d) {
+    lks::BCParams<T> b{};
+    for (int f = 0; f < 6; ++f) {
+        b.kind[f] = (f / 2 < d.dim) ? d.bc[f].kind : LKS_BC_PERIODIC;
+        b.rho[f] = (T)(d.bc[f].rho - 1.0);
+        for (int a = 0; a < 3; ++a) b.u[f][a] = (a < d.dim) ? (T)d.bc[f].u[a] : T(0);
+    }
+    return b;
+}
+
+template <typename T>
+lks::Design<T> design(const lks_ctx *c) {
+    lks::Design<T> s{};
+    s.kref = reinterpret_cast<const T *>(c->kref);
+    for (int a = 0; a < 3; ++a) {
+        s.nd[a] = c->d.nd[a];
+        s.xiG[a] = a < c->d.dim ? c->d.xi_G[a] : 0.0;
+    }
+    s.weight = c->d.weight == LKS_W_LIN ? 1 : 0;
+    return s;
+}
+
+lks::ObjParams obj_params(const lks_ctx *c, int n) {
+    lks::ObjParams o{};
+    const lks_objective &ob = c->d.objective;
+    o.kind = ob.kind;
+    o.active = ob.kind != LKS_OBJ_NONE && n >= ob.n0 && n <= ob.n1;
+    o.scale = c->obj_scale;
+    for (int a = 0; a < 3; ++a) {
+        o.centre[a] = ob.centre[a];
+        o.dir[a] = ob.dir[a];
+    }
+    o.mask = c->mask;
+    o.partials = o.active ? c->partials + (long long)(n - ob.n0) * c->L.max_blocks : nullptr;
+    return o;
+}
+
+// ---- timing: sample every k-th launch of a kernel kind with an event pair ------------------
+int flush_timing(lks_ctx *c) {
+    if (c->pool_used == 0) return LKS_OK;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (size_t i = 0; i < c->pool_used; ++i) {
+        float ms = 0;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->pool[i].a, c->pool[i].b));
+        c->samples[c->pool[i].kind] += 1;
+        c->total_ms[c->pool[i].kind] += ms;
+    }
+    c->pool_used = 0;
+    return LKS_OK;
+}
+
+struct Timed {
+    lks_ctx *c;
+    EventPair *ev = nullptr;
+    Timed(lks_ctx *cc, int kind) : c(cc) {
+        const long k = c->launches[kind]++;
+        if (c->every > 0 && k % c->every == 0 && c->pool_used < c->pool.size()) {
+            ev = &c->pool[c->pool_used++];
+            ev->kind = kind;
+            (void)hipEventRecord(ev->a, c->stream);
+        }
+    }
+    ~Timed() {
+        if (ev) (void)hipEventRecord(ev->b, c->stream);
+        if (ev && c->pool_used == c->pool.size()) (void)flush_timing(c);
+    }
+};
+
+template <typename T>
+int launch_step_fwd(lks_ctx *c, int n, const T *rin, const T *const uin[3], T *rout,
+                    T *const uout[3], int box_slot, bool objective) {
+    lks::FwdArgs<T> a{};
+    a.g = c->L.g;
+    a.bc = bc_params<T>(c->d);
+    a.A = (T)(4.5 * (1.0 / 6.0 - c->d.nu));
+    for (int k = 0; k < 3; ++k) a.gf[k] = k < c->d.dim ? (T)c->d.body_force[k] : T(0);
+    a.rin = rin;
+    a.rout = rout;
+    for (int k = 0; k < 3; ++k) {
+        a.uin[k] = k < c->d.dim ? uin[k] : nullptr;
+        a.uout[k] = k < c->d.dim ? uout[k] : nullptr;
+    }
+    a.kstatic = reinterpret_cast<const T *>(c->kstatic);
+    a.des = design<T>(c);
+    a.m = c->L.steps[n];
+    a.box = c->L.box;
+    if (box_slot >= 0) {
+        T *b = reinterpret_cast<T *>(c->box) + (long long)box_slot * (1 + c->d.dim) * c->L.box.cells;
+        a.kbox = b;
+        for (int k = 0; k < 3; ++k) a.usbox[k] = k < c->d.dim ? b + (1 + k) * c->L.box.cells : nullptr;
+    }
+    a.obj = obj_params(c, n);
+    if (!objective) a.obj.active = 0;
+    hipError_t e;
+    {
+        Timed t(c, 0);
+        e = c->d.dim == 2 ? lks::launch_fwd2d<T>(a, c->stream)
+                          : lks::launch_fwd3d<T>(a, c->d.lattice, c->stream);
+    }
+    HIPCHK(c, e);
+    return LKS_OK;
+}
+
+template <typename T>
+struct Fields {
+    T *r;
+    T *u[3];
+};
+
+template <typename T>
+Fields<T> state_fields(lks_ctx *c, char *base) {  // (1 + dim) consecutive fields
+    Fields<T> f{};
+    f.r = reinterpret_cast<T *>(base);
+    for (int k = 0; k < 3; ++k)
+        f.u[k] = k < c->d.dim ? reinterpret_cast<T *>(c->field(base, 1 + k)) : nullptr;
+    return f;
+}
+
+template <typename T>
+void traj_slot(lks_ctx *c, int j, T *u[3]) {  // dim consecutive fields per slot
+    for (int k = 0; k < 3; ++k)
+        u[k] = k < c->d.dim ? reinterpret_cast<T *>(c->field(c->traj, (long long)j * c->d.dim + k))
+                            : nullptr;
+}
+
+template <typename T>
+int copy_fields(lks_ctx *c, T *dst, const T *src, int nfields) {
+    HIPCHK(c, hipMemcpyAsync(dst, src, (size_t)nfields * c->L.F * sizeof(T), hipMemcpyDeviceToDevice,
+                             c->stream));
+    return LKS_OK;
+}
+
+template <typename T>
+int forward_impl(lks_ctx *c, const void *gamma, double *J) {
+    const Layout &L = c->L;
+    const int D = c->d.dim, N = c->d.nsteps, K = L.K, S = L.S;
+    int rc;
+    c->have_fwd = c->have_adj = false;
+    HIPCHK(c, hipMemcpyAsync(c->gamma, gamma, L.nd * sizeof(T), hipMemcpyDefault, c->stream));
+    HIPCHK(c, lks::launch_design_prep<T>(reinterpret_cast<const T *>(c->gamma),
+                                         reinterpret_cast<T *>(c->kref), c->kprime, L.nd,
+                                         c->d.interp == LKS_INTERP_PAPER ? 0 : 1,
+                                         c->d.kappa_max, c->d.q, c->stream));
+    HIPCHK(c, lks::launch_fill<double>(c->jn, 0.0, N + 1, c->stream));
+
+    Fields<T> st[2] = {state_fields<T>(c, c->state), state_fields<T>(c, c->field(c->state, 1 + D))};
+    {
+        lks::InitArgs<T> ia{};
+        ia.g = L.g;
+        ia.bc = bc_params<T>(c->d);
+        ia.r0 = (T)(c->d.rho0 - 1.0);
+        for (int k = 0; k < 3; ++k) ia.u0[k] = k < D ? (T)c->d.u0[k] : T(0);
+        if (c->init) {
+            Fields<T> in = state_fields<T>(c, c->init);
+            ia.rinit = in.r;
+            for (int k = 0; k < 3; ++k) ia.uinit[k] = in.u[k];
+        }
+        ia.rout = st[0].r;
+        for (int k = 0; k < 3; ++k) ia.uout[k] = st[0].u[k];
+        HIPCHK(c, lks::launch_init<T>(ia, c->stream));
+    }
+    int cur = 0;
+    for (int n = 1; n <= N; ++n) {
+        const int seg = (n - 1) / K, j = n - seg * K;
+        const bool last = seg == S - 1 && !L.fwd_only;
+        if (j == 1) {
+            T *ck = reinterpret_cast<T *>(c->field(c->ckpt, (long long)seg * (1 + D)));
+            if ((rc = copy_fields<T>(c, ck, st[cur].r, 1))) return rc;
+            if ((rc = copy_fields<T>(c, reinterpret_cast<T *>(c->field(reinterpret_cast<char *>(ck), 1)),
+                                     st[cur].u[0], D)))
+                return rc;
+            if (last) {
+                T *t0[3];
+                traj_slot<T>(c, 0, t0);
+                if ((rc = copy_fields<T>(c, t0[0], st[cur].u[0], D))) return rc;
+            }
+        }
+        T *uin[3], *uout[3];
+        if (last) {
+            traj_slot<T>(c, j - 1, uin);
+            traj_slot<T>(c, j, uout);
+        } else {
+            for (int k = 0; k < 3; ++k) {
+                uin[k] = st[cur].u[k];
+                uout[k] = st[1 - cur].u[k];
+            }
+        }
+        if ((rc = launch_step_fwd<T>(c, n, st[cur].r, uin, st[1 - cur].r, uout, last ? j - 1 : -1, true)))
+            return rc;
+        cur = 1 - cur;
+    }
+    if (c->d.objective.kind != LKS_OBJ_NONE)  // j^n of every step of the window, in block order
+        HIPCHK(c, lks::launch_reduce_steps(c->partials, L.max_blocks, lks::fwd_blocks(L.g, c->d.lattice),
+                                           c->d.objective.n0,
+                                           c->d.objective.n1, c->obj_scale,
+                                           c->jn + 0, c->stream));
+    // keep X^N: the trajectory store is reused by the reverse sweep
+    {
+        Fields<T> fin = state_fields<T>(c, c->fin);
+        T *ul[3];
+        if (L.fwd_only) {
+            for (int k = 0; k < 3; ++k) ul[k] = st[cur].u[k];
+        } else {
+            traj_slot<T>(c, N - (S - 1) * K, ul);
+        }
+        if ((rc = copy_fields<T>(c, fin.r, st[cur].r, 1))) return rc;
+        if ((rc = copy_fields<T>(c, fin.u[0], ul[0], D))) return rc;
+        HIPCHK(c, lks::launch_fill<int>(c->flag, 0, 1, c->stream));
+        HIPCHK(c, lks::launch_nonfinite<T>(fin.r, (long long)(1 + D) * L.F, c->flag, c->stream));
+    }
+    std::vector<double> jn(N + 1);
+    int flag = 0;
+    HIPCHK(c, hipMemcpyAsync(jn.data(), c->jn, (N + 1) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if ((rc = flush_timing(c))) return rc;
+    double acc = 0.0;
+    for (int n = 0; n <= N; ++n) acc += jn[n];
+    if (J) *J = acc;
+    if (flag) {
+        c->err = "non-finite value in the final state";
+        return LKS_ENONFINITE;
+    }
+    c->have_fwd = true;
+    return LKS_OK;
+}
+
+template <typename T>
+int adjoint_impl(lks_ctx *c) {
+    const Layout &L = c->L;
+    const int D = c->d.dim, N = c->d.nsteps, K = L.K, S = L.S;
+    int rc;
+    Fields<T> st[2] = {state_fields<T>(c, c->state), state_fields<T>(c, c->field(c->state, 1 + D))};
+    Fields<T> ad[2] = {state_fields<T>(c, c->adj), state_fields<T>(c, c->field(c->adj, 1 + D))};
+    HIPCHK(c, lks::launch_fill<T>(ad[0].r, T(0), (long long)(1 + D) * L.F, c->stream));
+    HIPCHK(c, lks::launch_fill<double>(c->G, 0.0, L.nd, c->stream));
+    int acur = 0;
+    for (int seg = S - 1; seg >= 0; --seg) {
+        const int n0 = seg * K + 1, n1 = std::min((seg + 1) * K, N);
+        if (seg != S - 1) {  // restore the checkpoint and recompute the segment
+            const T *ck = reinterpret_cast<const T *>(c->field(c->ckpt, (long long)seg * (1 + D)));
+            T *t0[3];
+            traj_slot<T>(c, 0, t0);
+            if ((rc = copy_fields<T>(c, st[0].r, ck, 1))) return rc;
+            if ((rc = copy_fields<T>(c, t0[0], ck + L.F, D))) return rc;
+            int cur = 0;
+            for (int n = n0; n <= n1; ++n) {
+                const int j = n - seg * K;
+                T *uin[3], *uout[3];
+                traj_slot<T>(c, j - 1, uin);
+                traj_slot<T>(c, j, uout);
+                if ((rc = launch_step_fwd<T>(c, n, st[cur].r, uin, st[1 - cur].r, uout, j - 1, false)))
+                    return rc;
+                cur = 1 - cur;
+            }
+        }
+        for (int n = n1; n >= n0; --n) {
+            const int j = n - seg * K;
+            lks::AdjArgs<T> a{};
+            a.g = L.g;
+            a.bc = bc_params<T>(c->d);
+            a.A = (T)(4.5 * (1.0 / 6.0 - c->d.nu));
+            a.Pin = ad[acur].r;
+            a.Pout = ad[1 - acur].r;
+            T *up[3], *uc[3];
+            traj_slot<T>(c, j - 1, up);
+            traj_slot<T>(c, j, uc);
+            for (int k = 0; k < 3; ++k) {
+                a.Vin[k] = ad[acur].u[k];
+                a.Vout[k] = ad[1 - acur].u[k];
+                a.uprev[k] = up[k];
+                a.ucur[k] = uc[k];
+            }
+            a.kstatic = reinterpret_cast<const T *>(c->kstatic);
+            const T *b = reinterpret_cast<const T *>(c->box) + (long long)(j - 1) * (1 + D) * L.box.cells;
+            a.kbox = b;
+            for (int k = 0; k < 3; ++k) a.usbox[k] = k < D ? b + (1 + k) * L.box.cells : nullptr;
+            a.kbar = reinterpret_cast<T *>(c->kbar);
+            a.box = L.box;
+            a.m = L.steps[n];
+            a.obj = obj_params(c, n);
+            hipError_t e;
+            {
+                Timed t(c, 1);
+                e = D == 2 ? lks::launch_adj2d<T>(a, c->stream) : lks::launch_adj3d<T>(a, c->d.lattice, c->stream);
+            }
+            HIPCHK(c, e);
+            lks::SensArgs<T> sa{};
+            sa.kbar = a.kbar;
+            sa.box = L.box;
+            sa.m = L.steps[n];
+            sa.des = design<T>(c);
+            sa.dim = D;
+            sa.G = c->G;
+            {
+                Timed t(c, 2);
+                e = lks::launch_sens<T>(sa, c->stream);
+            }
+            HIPCHK(c, e);
+            acur = 1 - acur;
+        }
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if ((rc = flush_timing(c))) return rc;
+    c->have_adj = true;
+    return LKS_OK;
+}
+
+template <typename T>
+int upload_padded(lks_ctx *c, char *dst, const double *src, int nfields) {
+    const Layout &L = c->L;
+    std::vector<T> h((size_t)nfields * L.F, T(0));
+    for (int f = 0; f < nfields; ++f)
+        for (long long z = 0; z < L.g.n[2]; ++z)
+            for (long long y = 0; y < L.g.n[1]; ++y)
+                for (long long x = 0; x < L.g.n[0]; ++x)
+                    h[f * L.F + x + y * L.g.sy + z * L.g.sz] =
+                        (T)src[f * L.ncell + x + L.g.n[0] * (y + L.g.n[1] * z)];
+    HIPCHK(c, hipMemcpy(dst, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+    return LKS_OK;
+}
+
+int create_impl(const lks_desc *d, lks_ctx *c) {
+    int rc;
+    c->d = *d;
+    c->motion.assign(d->motion, d->motion + d->nsteps + 1);
+    c->d.motion = c->motion.data();
+    c->stream = reinterpret_cast<hipStream_t>(d->stream);
+    HIPCHK(c, hipGetDevice(&c->dev));
+    const Layout &L = c->L;
+    const int D = d->dim;
+    const size_t e = L.esz;
+    void *p;
+#define ALLOC(member, bytes)                                        \
+    if ((rc = dalloc(c, (bytes), &p)) != LKS_OK) return rc;         \
+    c->member = reinterpret_cast<decltype(c->member)>(p);
+    ALLOC(state, L.b_state)
+    ALLOC(ckpt, L.b_ckpt)
+    ALLOC(traj, L.b_traj)
+    ALLOC(box, L.b_box)
+    ALLOC(kbar, L.b_kbar)
+    ALLOC(adj, L.b_adj)
+    ALLOC(fin, L.b_final)
+    ALLOC(gamma, L.nd * e)
+    ALLOC(kref, L.nd * e)
+    ALLOC(sens, L.nd * e)
+    ALLOC(kprime, L.nd * 8)
+    ALLOC(G, L.nd * 8)
+    ALLOC(jn, (d->nsteps + 1) * 8)
+    ALLOC(partials, (d->objective.kind == LKS_OBJ_NONE ? 1 : (d->objective.n1 - d->objective.n0 + 1)) *
+                        L.max_blocks * 8)
+    ALLOC(counter, 64)
+    c->flag = reinterpret_cast<int *>(reinterpret_cast<char *>(c->counter) + 32);
+    HIPCHK(c, hipMemset(c->counter, 0, 64));
+    // padded row tails are never written by the kernels: start every field buffer at zero
+    for (char *b : {c->state, c->ckpt, c->traj, c->adj, c->fin})
+        if (b) HIPCHK(c, hipMemset(b, 0, b == c->state ? L.b_state : b == c->ckpt ? L.b_ckpt
+                                         : b == c->traj ? L.b_traj : b == c->adj ? L.b_adj : L.b_final));
+    if (d->kappa_static) {
+        ALLOC(kstatic, L.F * e)
+        rc = e == 8 ? upload_padded<double>(c, c->kstatic, d->kappa_static, 1)
+                    : upload_padded<float>(c, c->kstatic, d->kappa_static, 1);
+        if (rc) return rc;
+    }
+    if (d->rho_init || d->u_init) {
+        ALLOC(init, (1 + D) * L.F * e)
+        std::vector<double> h((size_t)(1 + D) * L.ncell);
+        for (long long i = 0; i < L.ncell; ++i) h[i] = (d->rho_init ? d->rho_init[i] : d->rho0) - 1.0;
+        for (int k = 0; k < D; ++k)
+            for (long long i = 0; i < L.ncell; ++i)
+                h[(1 + k) * L.ncell + i] = d->u_init ? d->u_init[k * L.ncell + i] : d->u0[k];
+        rc = e == 8 ? upload_padded<double>(c, c->init, h.data(), 1 + D)
+                    : upload_padded<float>(c, c->init, h.data(), 1 + D);
+        if (rc) return rc;
+    }
+    long long mcount = L.ncell;
+    if (d->objective.kind != LKS_OBJ_NONE && d->objective.mask) {
+        ALLOC(mask, L.F)
+        std::vector<uint8_t> h(L.F, 0);
+        mcount = 0;
+        for (long long z = 0; z < L.g.n[2]; ++z)
+            for (long long y = 0; y < L.g.n[1]; ++y)
+                for (long long x = 0; x < L.g.n[0]; ++x) {
+                    const uint8_t v = d->objective.mask[x + L.g.n[0] * (y + L.g.n[1] * z)] ? 1 : 0;
+                    h[x + y * L.g.sy + z * L.g.sz] = v;
+                    mcount += v;
+                }
+        HIPCHK(c, hipMemcpy(c->mask, h.data(), L.F, hipMemcpyHostToDevice));
+    }
+#undef ALLOC
+    c->d.rho_init = c->d.u_init = c->d.kappa_static = nullptr;
+    c->d.objective.mask = nullptr;
+    c->obj_scale = 1.0;
+    if (d->objective.normalize & LKS_NORM_TIME) c->obj_scale /= (double)(d->objective.n1 - d->objective.n0 + 1);
+    if (d->objective.normalize & LKS_NORM_MASK) c->obj_scale /= (double)std::max(1LL, mcount);
+    return LKS_OK;
+}
+
+int set_err(lks_ctx *c, int code, const char *msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+}  // namespace
+
+// ====================================== C ABI ===============================================
+extern "C" {
+
+int lks_query_bytes(const lks_desc *d, size_t *bytes) {
+    Layout L;
+    std::string err;
+    int rc = plan(d, L, &err);
+    if (rc == LKS_ENOMEM && bytes) {
+        *bytes = L.bytes;
+        return LKS_OK;
+    }
+    if (rc) {
+        g_create_error = err;
+        return rc;
+    }
+    if (!bytes) return LKS_EINVAL;
+    *bytes = L.bytes;
+    return LKS_OK;
+}
+
+int lks_create(const lks_desc *d, lks_ctx **out) {
+    if (!out) {
+        g_create_error = "out is NULL";
+        return LKS_EINVAL;
+    }
+    *out = nullptr;
+    lks_ctx *c = new (std::nothrow) lks_ctx();
+    if (!c) {
+        g_create_error = "host allocation failed";
+        return LKS_ENOMEM;
+    }
+    int rc = plan(d, c->L, &g_create_error);
+    if (rc == LKS_OK) rc = create_impl(d, c);
+    if (rc != LKS_OK) {
+        if (!c->err.empty()) g_create_error = c->err;
+        lks_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return LKS_OK;
+}
+
+void lks_destroy(lks_ctx *c) {
+    if (!c) return;
+    if (c->stream || !c->allocs.empty()) (void)hipStreamSynchronize(c->stream);
+    for (void *p : c->allocs) (void)hipFree(p);
+    for (auto &ev : c->pool) {
+        if (ev.a) (void)hipEventDestroy(ev.a);
+        if (ev.b) (void)hipEventDestroy(ev.b);
+    }
+    delete c;
+}
+
+int lks_forward(lks_ctx *c, const void *gamma, double *J) {
+    if (!c) return LKS_EINVAL;
+    if (!gamma) return set_err(c, LKS_EINVAL, "gamma is NULL");
+    try {
+        return c->L.esz == 8 ? forward_impl<double>(c, gamma, J) : forward_impl<float>(c, gamma, J);
+    } catch (...) {
+        return set_err(c, LKS_ENOMEM, "host exception in lks_forward");
+    }
+}
+
+int lks_adjoint(lks_ctx *c) {
+    if (!c) return LKS_EINVAL;
+    if (c->L.fwd_only) return set_err(c, LKS_ESTATE, "the objective is NONE: nothing to differentiate");
+    if (!c->have_fwd) return set_err(c, LKS_ESTATE, "lks_adjoint needs a successful lks_forward first");
+    try {
+        return c->L.esz == 8 ? adjoint_impl<double>(c) : adjoint_impl<float>(c);
+    } catch (...) {
+        return set_err(c, LKS_ENOMEM, "host exception in lks_adjoint");
+    }
+}
+
+int lks_sensitivity(lks_ctx *c, void *dJdgamma) {
+    if (!c) return LKS_EINVAL;
+    if (!dJdgamma) return set_err(c, LKS_EINVAL, "output is NULL");
+    if (!c->have_adj) return set_err(c, LKS_ESTATE, "lks_sensitivity needs lks_adjoint after the last lks_forward");
+    const long long nd = c->L.nd;
+    hipError_t e = c->L.esz == 8
+        ? lks::launch_sens_finish<double>(c->kprime, c->G, reinterpret_cast<double *>(c->sens), nd, c->stream)
+        : lks::launch_sens_finish<float>(c->kprime, c->G, reinterpret_cast<float *>(c->sens), nd, c->stream);
+    HIPCHK(c, e);
+    HIPCHK(c, hipMemcpyAsync(dJdgamma, c->sens, nd * c->L.esz, hipMemcpyDefault, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LKS_OK;
+}
+
+int lks_read_state(lks_ctx *c, int which, void *drho, void *u) {
+    if (!c) return LKS_EINVAL;
+    if (!c->have_fwd) return set_err(c, LKS_ESTATE, "no forward state yet");
+    const Layout &L = c->L;
+    const int D = c->d.dim;
+    char *base;
+    if (which == LKS_STATE_FINAL) base = c->fin;
+    else if (which >= 0 && which < L.S && (L.S > 1 || which == 0)) base = c->field(c->ckpt, (long long)which * (1 + D));
+    else return set_err(c, LKS_EINVAL, "unknown state index");
+    const size_t e = L.esz;
+    const size_t rows = (size_t)L.g.n[1] * L.g.n[2];
+    if (drho)
+        HIPCHK(c, hipMemcpy2DAsync(drho, L.g.n[0] * e, base, L.pitch * e, L.g.n[0] * e, rows,
+                                   hipMemcpyDefault, c->stream));
+    if (u)
+        for (int k = 0; k < D; ++k)
+            HIPCHK(c, hipMemcpy2DAsync(static_cast<char *>(u) + (size_t)k * L.ncell * e, L.g.n[0] * e,
+                                       c->field(base, 1 + k), L.pitch * e, L.g.n[0] * e, rows,
+                                       hipMemcpyDefault, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LKS_OK;
+}
+
+int lks_read_objective_steps(lks_ctx *c, double *jn) {
+    if (!c || !jn) return LKS_EINVAL;
+    if (!c->have_fwd) return set_err(c, LKS_ESTATE, "no forward yet");
+    HIPCHK(c, hipMemcpyAsync(jn, c->jn, (c->d.nsteps + 1) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LKS_OK;
+}
+
+int lks_set_timing(lks_ctx *c, int every) {
+    if (!c || every < 0) return LKS_EINVAL;
+    int rc = flush_timing(c);
+    if (rc) return rc;
+    c->every = every;
+    for (int k = 0; k < 3; ++k) c->launches[k] = c->samples[k] = 0, c->total_ms[k] = 0;
+    if (every > 0 && c->pool.empty()) {
+        c->pool.resize(512);
+        // device-scope events: no system-wide cache release around the timed kernel
+        for (auto &ev : c->pool) {
+            if (hipEventCreateWithFlags(&ev.a, hipEventDisableSystemFence) != hipSuccess)
+                HIPCHK(c, hipEventCreate(&ev.a));
+            if (hipEventCreateWithFlags(&ev.b, hipEventDisableSystemFence) != hipSuccess)
+                HIPCHK(c, hipEventCreate(&ev.b));
+        }
+    }
+    return LKS_OK;
+}
+
+int lks_kernel_timing(lks_ctx *c, int kind, long *count, double *mean_ms) {
+    if (!c || kind < 0 || kind > 2) return LKS_EINVAL;
+    int rc = flush_timing(c);
+    if (rc) return rc;
+    if (count) *count = c->samples[kind];
+    if (mean_ms) *mean_ms = c->samples[kind] ? c->total_ms[kind] / c->samples[kind] : 0.0;
+    (void)kind_name;
+    return LKS_OK;
+}
+
+const char *lks_last_error(const lks_ctx *c) {
+    if (!c) return g_create_error.c_str();
+    return c->err.c_str();
+}
+
+const char *lks_strerror(int code) {
+    switch (code) {
+    case LKS_OK: return "ok";
+    case LKS_EINVAL: return "invalid argument";
+    case LKS_ENOMEM: return "out of memory or over the HBM budget";
+    case LKS_ESTATE: return "call out of order";
+    case LKS_ENONFINITE: return "non-finite state";
+    case LKS_EDEVICE: return "HIP runtime error";
+    case LKS_EUNSUPPORTED: return "unsupported";
+    }
+    return "unknown error";
+}
+
+}  // extern "C"

@@ -1,0 +1,296 @@
+// Device helpers shared by the 2D and 3D kernels: the transfer gather (design -> analysis), the
+// composite boundary rules, the objective densities and deterministic block reductions.
+#pragma once
+
+#include "lks_internal.hpp"
+
+namespace lks {
+
+enum { BC_PERIODIC = 0, BC_VELOCITY = 1, BC_PRESSURE = 2, BC_ZERO_GRADIENT = 3, BC_NOSLIP = 4 };
+enum { OBJ_NONE = -1, OBJ_POWER = 0, OBJ_DRAG = 1, OBJ_TORQUE = 2, OBJ_J1 = 3, OBJ_J2 = 4,
+       OBJ_MASS = 5 };
+
+constexpr int kBlock = 256;
+
+// wrap a coordinate onto a periodic axis; false if it leaves a non-periodic axis
+__device__ __forceinline__ bool wrapc(int &v, int n, int per) {
+    if (v >= 0 && v < n) return true;
+    if (!per) return false;
+    v %= n;
+    if (v < 0) v += n;
+    return true;
+}
+
+__device__ __forceinline__ bool on_face(const Geom &g, int a, int c) {
+    return !g.per[a] && (c == 0 || c == g.n[a] - 1);
+}
+
+__device__ __forceinline__ float cospi_t(float v) { return cospif(v); }
+__device__ __forceinline__ double cospi_t(double v) { return cospi(v); }
+
+// Transfer weight w(r) (Sec. 2.3 weight functions): LIN hat, or Peskin's cosine (1 + cos) / 4.
+template <typename T>
+__device__ __forceinline__ T wk(int weight, T d) {
+    T a = fabs(d);
+    if (weight == 1) return a < T(1) ? T(1) - a : T(0);
+    return a < T(2) ? T(0.25) * (T(1) + cospi_t(d * T(0.5))) : T(0);
+}
+
+// kappa(x) = sum_xi W(x - x_ref(xi)) kappa_ref(xi) and u_S(x) = sum_xi W u_ref(xi) at one analysis
+// node (Eqs. brinkman_ref, velocity_ref), evaluated as a gather: x is mapped back into the
+// design frame, p = R^T (x - xG) + xi_G, and the design nodes whose image can lie within the
+// kernel support of x are scanned.  x - x_ref(xi) = R (p - xi); u_ref is affine in xi, so
+// sum W u_ref = Omega x ((x - xG) sum W - sum W (x - x_ref)) + uG sum W.
+template <typename T, int DIM>
+__device__ void gather_kappa(const Design<T> &des, const StepMotion &m, int x, int y, int z,
+                             T &kap, T us[3]) {
+    constexpr int dim = DIM;
+    const double dx = x - m.xG[0], dy = y - m.xG[1], dz = (dim == 3) ? z - m.xG[2] : 0.0;
+    double p[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) p[b] = m.R[b] * dx + m.R[3 + b] * dy + m.R[6 + b] * dz + des.xiG[b];
+    const double s = des.weight == 1 ? 1.0 : 2.0;
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+#pragma unroll
+    for (int b = 0; b < dim; ++b) {
+        double h = 0.0;
+#pragma unroll
+        for (int a = 0; a < dim; ++a) h += fabs(m.R[3 * a + b]);
+        h *= s;
+        lo[b] = max(0, (int)ceil(p[b] - h));
+        hi[b] = min(des.nd[b] - 1, (int)floor(p[b] + h));
+    }
+    T R[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) R[i] = (T)m.R[i];
+    T f[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int b = 0; b < dim; ++b) f[b] = (T)(p[b] - lo[b]);
+    T d0[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) d0[a] = R[3 * a] * f[0] + R[3 * a + 1] * f[1] + R[3 * a + 2] * f[2];
+    T sW = 0, sWk = 0, sWd[3] = {0, 0, 0};
+    for (int k = lo[2]; k <= hi[2]; ++k) {
+        const T fk = (T)(k - lo[2]);
+        for (int j = lo[1]; j <= hi[1]; ++j) {
+            const T fj = (T)(j - lo[1]);
+            const T* krow = des.kref + (long long)des.nd[0] * (j + (long long)des.nd[1] * k);
+            for (int i = lo[0]; i <= hi[0]; ++i) {
+                const T fi = (T)(i - lo[0]);
+                T d[3] = {T(0), T(0), T(0)}, W = T(1);
+#pragma unroll
+                for (int a = 0; a < dim; ++a) {
+                    d[a] = d0[a] - fi * R[3 * a] - fj * R[3 * a + 1] - fk * R[3 * a + 2];
+                    W *= wk<T>(des.weight, d[a]);
+                }
+                if (W == T(0)) continue;
+                sW += W;
+                sWk += W * krow[i];
+#pragma unroll
+                for (int a = 0; a < dim; ++a) sWd[a] += W * d[a];
+            }
+        }
+    }
+    kap = sWk;
+    const double r0 = dx * (double)sW - (double)sWd[0];
+    const double r1 = dy * (double)sW - (double)sWd[1];
+    const double r2 = dz * (double)sW - (double)sWd[2];
+    us[0] = (T)(m.Om[1] * r2 - m.Om[2] * r1 + m.uG[0] * (double)sW);
+    us[1] = (T)(m.Om[2] * r0 - m.Om[0] * r2 + m.uG[1] * (double)sW);
+    us[2] = dim == 3 ? (T)(m.Om[0] * r1 - m.Om[1] * r0 + m.uG[2] * (double)sW) : T(0);
+}
+
+__device__ __forceinline__ bool in_box(const StepMotion &m, int dim, int x, int y, int z) {
+    bool in = x >= m.lo[0] && x <= m.hi[0] && y >= m.lo[1] && y <= m.hi[1];
+    if (dim == 3) in = in && z >= m.lo[2] && z <= m.hi[2];
+    return in;
+}
+
+__device__ __forceinline__ long long box_index(const BoxGeom &b, const StepMotion &m, int dim,
+                                               int x, int y, int z) {
+    return (x - m.lo[0]) + (long long)(y - m.lo[1]) * b.bsy +
+           (dim == 3 ? (long long)(z - m.lo[2]) * b.bsz : 0LL);
+}
+
+// ---- composite boundary rules ------------------------------------------------------------
+// Faces are applied in the order x-, x+, y-, y+, z-, z+ and each face rule reads the next node
+// inward, which is already final when that face is applied.  So a face node p takes its value
+// from exactly one interior node s (p shifted inward along each face it lies on), and each
+// component either survives every face of p's chain (copied from s) or is fixed by the latest
+// face of the chain that prescribes it.  comp 0 = rho, comp 1 + b = u_b.
+__device__ __forceinline__ bool bc_copies(int kind, int comp, int axis) {
+    if (comp == 0) return kind == BC_VELOCITY || kind == BC_NOSLIP || kind == BC_ZERO_GRADIENT;
+    return kind == BC_ZERO_GRADIENT || (kind == BC_PRESSURE && comp - 1 == axis);
+}
+
+template <typename T>
+__device__ __forceinline__ T bc_const(const BCParams<T> &bc, int f, int comp) {
+    return comp == 0 ? bc.rho[f] : bc.u[f][comp - 1];
+}
+
+// side[a] = 0 if interior node c is next to face a-, 1 if next to a+, -1 otherwise; returns the
+// bit set of adjacent axes
+template <int DIM>
+__device__ __forceinline__ int adjacent_faces(const Geom &g, const int c[3], int side[3]) {
+    int bits = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        side[a] = -1;
+        if (a >= DIM || g.per[a]) continue;
+        if (c[a] == 1) side[a] = 0;
+        else if (c[a] == g.n[a] - 2) side[a] = 1;
+        if (side[a] >= 0) bits |= 1 << a;
+    }
+    return bits;
+}
+
+// Forward: write every face node whose chain ends at interior node c (value v[0..dim]).  The face
+// nodes are c shifted outward along each non-empty subset of the adjacent axes.
+template <typename T, int DIM, typename Emit>
+__device__ void push_boundary(const Geom &g, const BCParams<T> &bc, const int c[3], const T v[4],
+                              Emit &&emit) {
+    int side[3];
+    const int bits = adjacent_faces<DIM>(g, c, side);
+    if (bits == 0) return;
+    for (int mask = 1; mask < (1 << DIM); ++mask) {
+        if ((mask & bits) != mask) continue;
+        int p[3] = {c[0], c[1], c[2]};
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+            if ((mask >> a) & 1) p[a] = side[a] ? g.n[a] - 1 : 0;
+        T pv[4] = {v[0], v[1], v[2], v[3]};
+#pragma unroll
+        for (int comp = 0; comp <= DIM; ++comp) {
+            bool done = false;
+#pragma unroll
+            for (int a = DIM - 1; a >= 0; --a) {  // latest face of the chain first
+                if (done || !((mask >> a) & 1)) continue;
+                const int f = 2 * a + side[a];
+                if (!bc_copies(bc.kind[f], comp, a)) {
+                    pv[comp] = bc_const(bc, f, comp);
+                    done = true;
+                }
+            }
+        }
+        emit(p, pv);
+    }
+}
+
+// Reverse: the seeds that face nodes pass back to interior node c.  fetch(p, comp) returns the
+// seed of component comp at face node p; a component passes only if every face of the chain
+// copies it.  Adds into acc[0..dim].
+template <int DIM, typename Fetch, typename T>
+__device__ void gather_boundary_T(const Geom &g, const int kind[6], const int c[3], T acc[4],
+                                  Fetch &&fetch) {
+    int side[3];
+    const int bits = adjacent_faces<DIM>(g, c, side);
+    if (bits == 0) return;
+    for (int mask = 1; mask < (1 << DIM); ++mask) {
+        if ((mask & bits) != mask) continue;
+        int p[3] = {c[0], c[1], c[2]};
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+            if ((mask >> a) & 1) p[a] = side[a] ? g.n[a] - 1 : 0;
+#pragma unroll
+        for (int comp = 0; comp <= DIM; ++comp) {
+            bool pass = true;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a)
+                if ((mask >> a) & 1) pass = pass && bc_copies(kind[2 * a + side[a]], comp, a);
+            if (pass) acc[comp] += fetch(p, comp);
+        }
+    }
+}
+
+// ---- objective density and its partials (per node, unscaled, mask applied by the caller) --
+template <typename T>
+__device__ __forceinline__ double obj_density(const ObjParams &o, int x, int y, int z, double r,
+                                              const T u[3], T kap, const T us[3]) {
+    const double F0 = (double)kap * ((double)u[0] - (double)us[0]);
+    const double F1 = (double)kap * ((double)u[1] - (double)us[1]);
+    const double F2 = (double)kap * ((double)u[2] - (double)us[2]);
+    switch (o.kind) {
+    case OBJ_DRAG: return F0 * o.dir[0] + F1 * o.dir[1] + F2 * o.dir[2];
+    case OBJ_POWER: return F0 * (double)us[0] + F1 * (double)us[1] + F2 * (double)us[2];
+    case OBJ_TORQUE: {
+        const double r0 = x - o.centre[0], r1 = y - o.centre[1], r2 = z - o.centre[2];
+        return o.dir[0] * (r1 * F2 - r2 * F1) + o.dir[1] * (r2 * F0 - r0 * F2) +
+               o.dir[2] * (r0 * F1 - r1 * F0);
+    }
+    case OBJ_J1: return -(1.0 + r) / 3.0;  // r is rho - 1
+    case OBJ_J2: return -(o.dir[0] * (double)u[0] + o.dir[1] * (double)u[1] + o.dir[2] * (double)u[2]);
+    case OBJ_MASS: return 1.0 + r;
+    }
+    return 0.0;
+}
+
+// d(density)/d(rho, u) -> dP, dV[3]; d/d kappa needs u and is returned by obj_dkappa
+__device__ __forceinline__ void obj_dstate(const ObjParams &o, int x, int y, int z, double kap,
+                                           const double us[3], double &dP, double dV[3]) {
+    dP = 0.0;
+    dV[0] = dV[1] = dV[2] = 0.0;
+    switch (o.kind) {
+    case OBJ_DRAG:
+        for (int a = 0; a < 3; ++a) dV[a] = kap * o.dir[a];
+        break;
+    case OBJ_POWER:
+        for (int a = 0; a < 3; ++a) dV[a] = kap * us[a];
+        break;
+    case OBJ_TORQUE: {
+        const double r0 = x - o.centre[0], r1 = y - o.centre[1], r2 = z - o.centre[2];
+        dV[0] = kap * (o.dir[1] * r2 - o.dir[2] * r1);
+        dV[1] = kap * (o.dir[2] * r0 - o.dir[0] * r2);
+        dV[2] = kap * (o.dir[0] * r1 - o.dir[1] * r0);
+        break;
+    }
+    case OBJ_J1: dP = -1.0 / 3.0; break;
+    case OBJ_J2:
+        for (int a = 0; a < 3; ++a) dV[a] = -o.dir[a];
+        break;
+    case OBJ_MASS: dP = 1.0; break;
+    }
+}
+
+__device__ __forceinline__ double obj_dkappa(const ObjParams &o, int x, int y, int z,
+                                             const double u[3], const double us[3]) {
+    const double v0 = u[0] - us[0], v1 = u[1] - us[1], v2 = u[2] - us[2];
+    switch (o.kind) {
+    case OBJ_DRAG: return v0 * o.dir[0] + v1 * o.dir[1] + v2 * o.dir[2];
+    case OBJ_POWER: return v0 * us[0] + v1 * us[1] + v2 * us[2];
+    case OBJ_TORQUE: {
+        const double r0 = x - o.centre[0], r1 = y - o.centre[1], r2 = z - o.centre[2];
+        const double m0 = o.dir[1] * r2 - o.dir[2] * r1, m1 = o.dir[2] * r0 - o.dir[0] * r2,
+                     m2 = o.dir[0] * r1 - o.dir[1] * r0;
+        return v0 * m0 + v1 * m1 + v2 * m2;
+    }
+    }
+    return 0.0;
+}
+
+__device__ __forceinline__ bool obj_uses_kappa(int kind) {
+    return kind == OBJ_DRAG || kind == OBJ_POWER || kind == OBJ_TORQUE;
+}
+
+// ---- deterministic reductions ---------------------------------------------------------------
+// Sum over a 256-thread block in a fixed order; the result is valid on thread 0.
+__device__ __forceinline__ double block_sum(double v, double *sh4) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh4[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) t = (sh4[0] + sh4[1]) + (sh4[2] + sh4[3]);
+    return t;
+}
+
+// Every block stores its partial for this step; the partials of all steps are summed in block
+// order by one reduction kernel at the end of the sweep (no cross-block synchronisation here).
+__device__ __forceinline__ void store_partial(const ObjParams &o, double v, long long blin,
+                                              double *sh4) {
+    const double bs = block_sum(v, sh4);
+    if (threadIdx.x == 0) o.partials[blin] = bs;
+}
+
+}  // namespace lks

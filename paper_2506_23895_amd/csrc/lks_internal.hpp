@@ -1,0 +1,147 @@
+// Internal structures shared by the host runtime and the HIP kernels of the LKS library.
+// Nothing here is part of the C ABI (include/lks.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace lks {
+
+// Analysis grid: node (x, y, z) lives at x + y*sy + z*sz in every field (rows padded).
+struct Geom {
+    int dim;
+    int n[3];
+    int per[3];        // 1 if the axis is periodic (always 1 for axes >= dim)
+    long long sy, sz;  // element strides
+};
+
+// Boundary kinds per face (x-, x+, y-, y+, z-, z+); rho is stored as rho - 1.
+template <typename T>
+struct BCParams {
+    int kind[6];
+    T rho[6];
+    T u[6][3];
+};
+
+// Rigid motion at one step plus the footprint box of the mapped design grid (inclusive bounds).
+struct StepMotion {
+    double R[9];
+    double Om[3];
+    double xG[3];
+    double uG[3];
+    int lo[3];
+    int hi[3];
+};
+
+template <typename T>
+struct Design {
+    const T *kref;  // kappa_ref on the design grid
+    int nd[3];
+    double xiG[3];
+    int weight;     // 0 = COS4, 1 = LIN
+};
+
+// Footprint box store: fixed extent bn (max over steps), element strides.
+struct BoxGeom {
+    int bn[3];
+    long long bsy, bsz, cells;
+};
+
+struct ObjParams {
+    int kind;          // LKS_OBJ_* (-1 none)
+    int active;        // this step lies in the window
+    double scale;      // 1/(n1-n0+1) and/or 1/|mask|
+    double centre[3];
+    double dir[3];
+    const uint8_t *mask;    // padded like the fields, or null
+    double *partials;       // this step's row of per-block partials
+};
+
+template <typename T>
+struct FwdArgs {
+    Geom g;
+    BCParams<T> bc;
+    T A;
+    T gf[3];
+    const T *rin;
+    const T *uin[3];
+    T *rout;
+    T *uout[3];
+    const T *kstatic;
+    Design<T> des;
+    StepMotion m;
+    T *kbox;        // optional: kappa and u_S written on the footprint box
+    T *usbox[3];
+    BoxGeom box;
+    ObjParams obj;
+};
+
+template <typename T>
+struct AdjArgs {
+    Geom g;
+    BCParams<T> bc;
+    T A;
+    const T *Pin;
+    const T *Vin[3];
+    T *Pout;
+    T *Vout[3];
+    const T *uprev[3];  // input velocity of the forward step
+    const T *ucur[3];   // output velocity of the forward step
+    const T *kstatic;
+    const T *kbox;      // kappa and u_S of this step on the footprint box
+    const T *usbox[3];
+    T *kbar;            // adjoint of kappa on the footprint box (written)
+    BoxGeom box;
+    StepMotion m;
+    ObjParams obj;
+};
+
+template <typename T>
+struct SensArgs {
+    const T *kbar;
+    BoxGeom box;
+    StepMotion m;
+    Design<T> des;
+    int dim;
+    double *G;
+};
+
+template <typename T>
+struct InitArgs {
+    Geom g;
+    BCParams<T> bc;
+    T r0;
+    T u0[3];
+    const T *rinit;     // optional padded fields
+    const T *uinit[3];
+    T *rout;
+    T *uout[3];
+};
+
+// ---- launchers (defined in the .hip files) -----------------------------------------------
+template <typename T> hipError_t launch_fwd2d(const FwdArgs<T> &a, hipStream_t s);
+template <typename T> hipError_t launch_adj2d(const AdjArgs<T> &a, hipStream_t s);
+template <typename T> hipError_t launch_fwd3d(const FwdArgs<T> &a, int lattice, hipStream_t s);
+template <typename T> hipError_t launch_adj3d(const AdjArgs<T> &a, int lattice, hipStream_t s);
+template <typename T> hipError_t launch_sens(const SensArgs<T> &a, hipStream_t s);
+template <typename T> hipError_t launch_init(const InitArgs<T> &a, hipStream_t s);
+template <typename T>
+hipError_t launch_design_prep(const T *gamma, T *kref, double *kprime, long long nd, int interp,
+                              double kmax, double q, hipStream_t s);
+template <typename T>
+hipError_t launch_sens_finish(const double *kprime, const double *G, T *out, long long nd,
+                              hipStream_t s);
+template <typename T>
+hipError_t launch_fill(T *p, T v, long long count, hipStream_t s);
+template <typename T>
+hipError_t launch_nonfinite(const T *p, long long count, int *flag, hipStream_t s);
+// jn[n] = scale * sum_{b < nblocks} partials[(n - n0) * stride + b] for n in [n0, n1]
+hipError_t launch_reduce_steps(const double *partials, long long stride, long long nblocks, int n0,
+                               int n1, double scale, double *jn, hipStream_t s);
+
+// grid sizes of the stencil launches (used by the host to size the partials buffer)
+long long fwd_blocks(const Geom &g, int lattice);
+long long adj_blocks(const Geom &g, int lattice);
+
+}  // namespace lks

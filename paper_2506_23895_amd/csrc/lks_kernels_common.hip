@@ -1,0 +1,190 @@
+// Per-solve and per-reverse-step kernels shared by 2D and 3D:
+//   design prep   kappa_ref = I(gamma), I'(gamma) on the design grid (Sec. 2.3, first equation)
+//   init          X^0 with the composite boundary rules applied
+//   sens gather   G(xi) += sum_x W_n(x - x_ref(xi)) kappa_bar^n(x): the transpose of the transfer
+//                 as a gather onto each design node (one thread per design node, no atomics)
+//   sens finish   dJ/dgamma = I'(gamma) G (Sec. 2.4, sensitivity pulled back to the design grid)
+//   fill, non-finite scan
+#include "lks_device.hpp"
+
+namespace lks {
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_design_prep(const T *gamma, T *kref, double *kprime,
+                                                        long long nd, int interp, double kmax,
+                                                        double q) {
+    const long long i = blockIdx.x * (long long)kBlock + threadIdx.x;
+    if (i >= nd) return;
+    const double g = (double)gamma[i];
+    if (interp == 0) {  // gamma = 1 solid
+        const double den = (1.0 - g) + q;
+        kref[i] = (T)(kmax * q * g / den);
+        kprime[i] = kmax * q * (1.0 + q) / (den * den);
+    } else {            // gamma = 1 fluid
+        const double den = q + g;
+        kref[i] = (T)(kmax * q * (1.0 - g) / den);
+        kprime[i] = -kmax * q * (1.0 + q) / (den * den);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_init(const InitArgs<T> a) {
+    const Geom &g = a.g;
+    const long long ncell = (long long)g.n[0] * g.n[1] * g.n[2];
+    const long long t = blockIdx.x * (long long)kBlock + threadIdx.x;
+    if (t >= ncell) return;
+    const int x = (int)(t % g.n[0]);
+    const int y = (int)((t / g.n[0]) % g.n[1]);
+    const int z = (int)(t / ((long long)g.n[0] * g.n[1]));
+    if (on_face(g, 0, x) || on_face(g, 1, y) || (g.dim == 3 && on_face(g, 2, z))) return;
+    const long long idx = x + y * g.sy + z * g.sz;
+    T v[4];
+    v[0] = a.rinit ? a.rinit[idx] : a.r0;
+    for (int c = 0; c < 3; ++c) v[1 + c] = (c < g.dim) ? (a.uinit[0] ? a.uinit[c][idx] : a.u0[c]) : T(0);
+    a.rout[idx] = v[0];
+    for (int c = 0; c < g.dim; ++c) a.uout[c][idx] = v[1 + c];
+    const int c3[3] = {x, y, z};
+    push_boundary<T, 3>(g, a.bc, c3, v, [&](const int p[3], const T pv[4]) {
+        const long long pi = p[0] + p[1] * g.sy + p[2] * g.sz;
+        a.rout[pi] = pv[0];
+        for (int c = 0; c < g.dim; ++c) a.uout[c][pi] = pv[1 + c];
+    });
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_sens(const SensArgs<T> a) {
+    const long long ndn = (long long)a.des.nd[0] * a.des.nd[1] * a.des.nd[2];
+    const long long i = blockIdx.x * (long long)kBlock + threadIdx.x;
+    if (i >= ndn) return;
+    const int ix = (int)(i % a.des.nd[0]);
+    const int iy = (int)((i / a.des.nd[0]) % a.des.nd[1]);
+    const int iz = (int)(i / ((long long)a.des.nd[0] * a.des.nd[1]));
+    const double d0 = ix - a.des.xiG[0], d1 = iy - a.des.xiG[1],
+                 d2 = (a.dim == 3) ? iz - a.des.xiG[2] : 0.0;
+    double xr[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+        xr[r] = a.m.R[3 * r] * d0 + a.m.R[3 * r + 1] * d1 + a.m.R[3 * r + 2] * d2 + a.m.xG[r];
+    const double s = a.des.weight == 1 ? 1.0 : 2.0;
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int r = 0; r < a.dim; ++r) {
+        lo[r] = max(a.m.lo[r], (int)ceil(xr[r] - s));
+        hi[r] = min(a.m.hi[r], (int)floor(xr[r] + s));
+    }
+    double acc = 0.0;
+    for (int z = lo[2]; z <= hi[2]; ++z) {
+        const T wz = (a.dim == 3) ? wk<T>(a.des.weight, (T)(z - xr[2])) : T(1);
+        if (wz == T(0)) continue;
+        for (int y = lo[1]; y <= hi[1]; ++y) {
+            const T wy = wk<T>(a.des.weight, (T)(y - xr[1]));
+            if (wy == T(0)) continue;
+            for (int x = lo[0]; x <= hi[0]; ++x) {
+                const T wx = wk<T>(a.des.weight, (T)(x - xr[0]));
+                if (wx == T(0)) continue;
+                acc += (double)(wx * wy * wz) * (double)a.kbar[box_index(a.box, a.m, a.dim, x, y, z)];
+            }
+        }
+    }
+    a.G[i] += acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_sens_finish(const double *kprime, const double *G,
+                                                        T *out, long long nd) {
+    const long long i = blockIdx.x * (long long)kBlock + threadIdx.x;
+    if (i < nd) out[i] = (T)(kprime[i] * G[i]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fill(T *p, T v, long long count) {
+    const long long i = blockIdx.x * (long long)kBlock + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_nonfinite(const T *p, long long count, int *flag) {
+    const long long i = blockIdx.x * (long long)kBlock + threadIdx.x;
+    if (i < count && !isfinite(p[i])) atomicOr(flag, 1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce_steps(const double *partials, long long stride,
+                                                         long long nblocks, int n0, double scale,
+                                                         double *jn) {
+    __shared__ double sh4[4];
+    const int n = n0 + blockIdx.x;
+    const double *row = partials + (long long)blockIdx.x * stride;
+    double acc = 0.0;
+    for (long long i = threadIdx.x; i < nblocks; i += kBlock) acc += row[i];
+    const double t = block_sum(acc, sh4);
+    if (threadIdx.x == 0) jn[n] = t * scale;
+}
+
+static inline dim3 grid1(long long n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); }
+
+template <typename T>
+hipError_t launch_design_prep(const T *gamma, T *kref, double *kprime, long long nd, int interp,
+                              double kmax, double q, hipStream_t s) {
+    hipLaunchKernelGGL(k_design_prep<T>, grid1(nd), dim3(kBlock), 0, s, gamma, kref, kprime, nd,
+                       interp, kmax, q);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_init(const InitArgs<T> &a, hipStream_t s) {
+    const long long ncell = (long long)a.g.n[0] * a.g.n[1] * a.g.n[2];
+    hipLaunchKernelGGL(k_init<T>, grid1(ncell), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_sens(const SensArgs<T> &a, hipStream_t s) {
+    const long long ndn = (long long)a.des.nd[0] * a.des.nd[1] * a.des.nd[2];
+    hipLaunchKernelGGL(k_sens<T>, grid1(ndn), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_sens_finish(const double *kprime, const double *G, T *out, long long nd,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_sens_finish<T>, grid1(nd), dim3(kBlock), 0, s, kprime, G, out, nd);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fill(T *p, T v, long long count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill<T>, grid1(count), dim3(kBlock), 0, s, p, v, count);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_nonfinite(const T *p, long long count, int *flag, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_nonfinite<T>, grid1(count), dim3(kBlock), 0, s, p, count, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_steps(const double *partials, long long stride, long long nblocks, int n0,
+                               int n1, double scale, double *jn, hipStream_t s) {
+    if (n1 < n0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_steps, dim3(n1 - n0 + 1), dim3(kBlock), 0, s, partials, stride,
+                       nblocks, n0, scale, jn);
+    return hipGetLastError();
+}
+
+#define LKS_INST(T)                                                                               \
+    template hipError_t launch_design_prep<T>(const T *, T *, double *, long long, int, double,   \
+                                              double, hipStream_t);                               \
+    template hipError_t launch_init<T>(const InitArgs<T> &, hipStream_t);                         \
+    template hipError_t launch_sens<T>(const SensArgs<T> &, hipStream_t);                         \
+    template hipError_t launch_sens_finish<T>(const double *, const double *, T *, long long,     \
+                                              hipStream_t);                                       \
+    template hipError_t launch_fill<T>(T *, T, long long, hipStream_t);                           \
+    template hipError_t launch_nonfinite<T>(const T *, long long, int *, hipStream_t);
+LKS_INST(float)
+LKS_INST(double)
+template hipError_t launch_fill<unsigned int>(unsigned int *, unsigned int, long long, hipStream_t);
+template hipError_t launch_fill<int>(int *, int, long long, hipStream_t);
+#undef LKS_INST
+
+}  // namespace lks

@@ -1,0 +1,164 @@
+"""GPU parity of the 2D D2Q9 path (HIP kernels through the C ABI) against the FP64 CPU oracle.
+
+Tolerances: FP64 path within 1e-11 relative L2 (different summation order and reciprocal
+instead of division only); FP32 path within 1e-4 relative L2 on rho - 1 and u and 1e-3 on the
+sensitivity.  rho is compared as rho - 1 (the fluctuation), a stricter measure than rho.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import lks_inputs as I
+from parity_util import announce, compare, rel_l2, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+F64 = dict(tol_field=1e-11, tol_grad=1e-10, tol_J=1e-11)
+F32 = dict(tol_field=1e-4, tol_grad=1e-3, tol_J=1e-4)
+
+
+def _bc(kind, rho=1.0, u=(0.0, 0.0, 0.0)):
+    return {"kind": kind, "rho": rho, "u": u}
+
+
+def small(n=(70, 37), nd=(14, 12), N=60, K=0, prec="F64", obj="DRAG", weight="LIN",
+          interp="FLUID_ONE", bcs=None, motion="rotate", mask=None, norm=1, kmax=0.5, nu=0.04):
+    centre = ((n[0] - 1) / 2.0 + 0.3, (n[1] - 1) / 2.0 - 0.2, 0.0)
+    if motion == "rotate":
+        mot = I.motion_rotation(N, centre, 2 * math.pi / 90)
+    else:
+        mot = I.motion_heave(N, centre, 2.5, 2 * math.pi / 50, theta_amp=0.4)
+    return I.make_config(dim=2, lattice="D2Q9", n=n, nd=nd, nu=nu, nsteps=N, motion=mot,
+                         bcs=bcs or I.channel_bcs(2, 0.03),
+                         obj=I.objective(obj, 2, N, norm=norm, centre=centre,
+                                         direction=(0.8, 0.6, 0.0) if obj != "TORQUE" else (0, 0, 1),
+                                         mask=mask),
+                         u0=(0.03, 0, 0), weight=weight, interp=interp, kappa_max=kmax,
+                         precision=prec, checkpoint_every=K)
+
+
+def test_c1_fp64_full():
+    """64x64 channel, 24x24 rotating design, 400 steps, time-integrated power: FP64 parity."""
+    cfg = I.config_c1("F64")
+    announce("c1 fp64")
+    g = I.gamma_field(cfg["nd"], 2, 0)
+    res = compare(cfg, g, **F64)
+    print(res)
+
+
+def test_c1_fp32_full():
+    cfg = I.config_c1("F32")
+    announce("c1 fp32")
+    g = I.gamma_field(cfg["nd"], 2, 0)
+    print(compare(cfg, g, **F32))
+
+
+@pytest.mark.parametrize("K", [1, 7, 25])
+def test_checkpoint_segments_fp64(K):
+    """Ragged grid (70x37 spans two tiles in x and five in y with tails), checkpointed reverse
+    with segments that do and do not divide N; every checkpoint state is compared."""
+    cfg = small(K=K)
+    announce(f"checkpoint K={K}")
+    g = I.gamma_field(cfg["nd"], 2, 11)
+    compare(cfg, g, check_ckpt=True, **F64)
+
+
+CASES = {
+    "cos4_paper_power": dict(weight="COS4", interp="PAPER", obj="POWER", kmax=2.0),
+    "heave_torque": dict(motion="heave", obj="TORQUE"),
+    "j2": dict(obj="J2"),
+    "pressure_outlet": dict(bcs=[_bc("VELOCITY", 1.0, (0.03, 0, 0)), _bc("PRESSURE", 1.002, (0, 0.004, 0)),
+                                 _bc("NOSLIP", 1.0, (0.01, 0, 0)), _bc("ZERO_GRADIENT"),
+                                 _bc("PERIODIC"), _bc("PERIODIC")]),
+    "periodic_x": dict(bcs=[_bc("PERIODIC"), _bc("PERIODIC"), _bc("NOSLIP"),
+                            _bc("VELOCITY", 1.0, (0.02, 0, 0)), _bc("PERIODIC"), _bc("PERIODIC")]),
+    "fully_periodic": dict(bcs=I.periodic_bcs(), obj="POWER"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_variants_fp64(name):
+    cfg = small(K=13, **CASES[name])
+    announce(f"variant {name}")
+    g = I.gamma_field(cfg["nd"], 2, 3)
+    compare(cfg, g, **F64)
+
+
+def test_j1_boundary_mask_fp64():
+    n = (70, 37)
+    mask = np.zeros(n[::-1], dtype=np.uint8)
+    mask[0, :] = 1
+    mask[:, -1] = 1
+    mask[-1, 5:20] = 1
+    cfg = small(obj="J1", mask=mask.reshape(-1), norm=3, K=9)
+    announce("j1 boundary mask")
+    compare(cfg, I.gamma_field(cfg["nd"], 2, 4), **F64)
+
+
+def test_smallest_grid_fp64():
+    """4x4 analysis grid with walls (one interior 2x2 block), a single design node."""
+    N = 12
+    cfg = I.make_config(dim=2, lattice="D2Q9", n=(4, 4), nd=(1, 1), nu=0.1, nsteps=N,
+                        motion=I.motion_static(N, (1.5, 1.5, 0.0)), bcs=I.channel_bcs(2, 0.02),
+                        obj=I.objective("MASS", 1, N), u0=(0.02, 0, 0), precision="F64",
+                        weight="LIN", kappa_max=0.0, checkpoint_every=5)
+    # design node sits at (1.5, 1.5): support reaches x = 1..2 only (inside the interior)
+    announce("smallest grid")
+    compare(cfg, np.array([0.3]), **F64)
+
+
+def test_c3_copy96_fp32():
+    """Config-3 parameters on a 96x96 copy (24x24 design, 10000 steps, checkpoint every 100,
+    time-averaged drag), FP32 against the FP64 oracle."""
+    cfg = I.config_c3(n_side=96, nd_side=24, precision="F32")
+    announce("c3 copy 96 fp32")
+    g = I.gamma_field(cfg["nd"], 2, 2)
+    print(compare(cfg, g, **F32))
+
+
+def test_c3_full_grid_short_fp32():
+    """The benchmark's launch configuration (1024x1024 grid, 256x256 design, FP32, checkpoints)
+    on a horizon the oracle finishes quickly."""
+    cfg = I.config_c3(precision="F32", nsteps=24, checkpoint_every=10)
+    announce("c3 full grid 24 steps fp32")
+    g = I.gamma_field(cfg["nd"], 2, 2)
+    print(compare(cfg, g, **F32))
+
+
+def test_c2_full_grid_short_fp32():
+    cfg = I.config_c2(precision="F32", nsteps=12)
+    announce("c2 full grid 12 steps fp32")
+    g = I.gamma_field(cfg["nd"], 2, 1)
+    print(compare(cfg, g, **F32))
+
+
+def test_deterministic_repeat():
+    """Bitwise-identical results on a repeat run (no atomics in any accumulation)."""
+    cfg = small(K=10, prec="F32")
+    g = I.gamma_field(cfg["nd"], 2, 5).astype(np.float32)
+    announce("determinism")
+    a = run_gpu(cfg, g)
+    b = run_gpu(cfg, g)
+    assert a["J"] == b["J"]
+    assert np.array_equal(a["grad"], b["grad"])
+    assert np.array_equal(a["final"][1], b["final"][1])
+
+
+def test_device_io_path():
+    """io_on_device: gamma and dJ/dgamma as torch device tensors give the host path's results."""
+    import torch
+    from paper_2506_23895_amd import lks
+    cfg = small(K=10, prec="F32")
+    g = I.gamma_field(cfg["nd"], 2, 6).astype(np.float32)
+    announce("device io")
+    ref = run_gpu(cfg, g)
+    with lks.Solver(cfg, io_on_device=True) as s:
+        gt = torch.from_numpy(g).cuda()
+        J = s.forward(gt)
+        s.adjoint()
+        out = torch.empty_like(gt)
+        s.sensitivity(out)
+        torch.cuda.synchronize()
+    assert J == ref["J"]
+    assert np.array_equal(out.cpu().numpy(), ref["grad"].astype(np.float32))
