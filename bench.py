@@ -65,9 +65,13 @@ def bytes_per_lup(cfg: dict) -> dict:
     """Algorithmic HBM bytes per lattice update of each stencil kernel (what it must move)."""
     e = 8 if cfg["precision"] == "F64" else 4
     D = cfg["dim"]
+    # 2D adjoint: one fused kernel (read lambda, u^{n-1}; write lambda).  3D adjoint: a pointwise
+    # kernel (read lambda, write (P*, V*)) then the marching kernel (read (P*, V*), u^{n-1}; write
+    # lambda); the timed "adj_step" covers both launches.
+    adj = (2 * (1 + D) + D) * e if D == 2 else (2 * (1 + D) + 2 * (1 + D) + D) * e
     return {
         "fwd_step": (2 * (1 + D)) * e,          # read rho, u; write rho, u
-        "adj_step": (2 * (1 + D) + D) * e,      # read lambda, u^{n-1}; write lambda
+        "adj_step": adj,
     }
 
 

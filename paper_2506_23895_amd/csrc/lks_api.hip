@@ -46,7 +46,7 @@ struct Layout {
     size_t bytes = 0;
     // byte sizes of each allocation
     size_t b_state = 0, b_ckpt = 0, b_traj = 0, b_box = 0, b_kbar = 0, b_adj = 0, b_design = 0,
-           b_aux = 0, b_final = 0;
+           b_aux = 0, b_final = 0, b_pv = 0;
     long long max_blocks = 0;
     bool fwd_only = false;   // objective NONE: forward sweep only, no trajectory or adjoint storage
 };
@@ -196,7 +196,8 @@ int plan(const lks_desc *d, Layout &L, std::string *err) {
     L.b_adj = L.fwd_only ? 0 : 2 * nf * L.F * e;
     L.b_final = nf * L.F * e;
     L.b_design = (size_t)L.nd * (3 * e + 2 * 8);  // gamma, kref, sens out; kprime, G
-    L.max_blocks = std::max(lks::fwd_blocks(g, d->lattice), lks::adj_blocks(g, d->lattice));
+    L.max_blocks = lks::fwd_blocks(g, d->lattice, (int)L.esz);
+    L.b_pv = (D == 3 && !L.fwd_only) ? (size_t)4 * L.F * e : 0;  // (P*, V*) between the 3D adjoint kernels
     // objective partials: one row of per-block sums per step of the window, reduced at the end
     const long long obj_rows = d->objective.kind == LKS_OBJ_NONE ? 1 : (d->objective.n1 - d->objective.n0 + 1);
     L.b_aux = (size_t)(d->nsteps + 1) * 8 + (size_t)obj_rows * L.max_blocks * 8 + 64;
@@ -204,7 +205,7 @@ int plan(const lks_desc *d, Layout &L, std::string *err) {
     if (d->objective.kind != LKS_OBJ_NONE && d->objective.mask) L.b_aux += L.F;
     if (d->rho_init || d->u_init) L.b_aux += nf * L.F * e;
     L.bytes = L.b_state + L.b_ckpt + L.b_traj + L.b_box + L.b_kbar + L.b_adj + L.b_final +
-              L.b_design + L.b_aux;
+              L.b_design + L.b_aux + L.b_pv;
     if (d->hbm_budget_bytes && L.bytes > d->hbm_budget_bytes)
         return fail(err, LKS_ENOMEM, "context needs " + std::to_string(L.bytes) +
                                           " bytes, over the HBM budget");
@@ -227,7 +228,7 @@ struct lks_ctx {
     // device memory
     char *state = nullptr, *ckpt = nullptr, *traj = nullptr, *box = nullptr, *kbar = nullptr,
          *adj = nullptr, *fin = nullptr, *gamma = nullptr, *kref = nullptr, *sens = nullptr,
-         *kstatic = nullptr, *init = nullptr;
+         *kstatic = nullptr, *init = nullptr, *pv = nullptr;
     double *kprime = nullptr, *G = nullptr, *jn = nullptr, *partials = nullptr;
     unsigned int *counter = nullptr;
     int *flag = nullptr;
@@ -468,7 +469,7 @@ int forward_impl(lks_ctx *c, const void *gamma, double *J) {
         cur = 1 - cur;
     }
     if (c->d.objective.kind != LKS_OBJ_NONE)  // j^n of every step of the window, in block order
-        HIPCHK(c, lks::launch_reduce_steps(c->partials, L.max_blocks, lks::fwd_blocks(L.g, c->d.lattice),
+        HIPCHK(c, lks::launch_reduce_steps(c->partials, L.max_blocks, L.max_blocks,
                                            c->d.objective.n0,
                                            c->d.objective.n1, c->obj_scale,
                                            c->jn + 0, c->stream));
@@ -557,6 +558,10 @@ int adjoint_impl(lks_ctx *c) {
             a.box = L.box;
             a.m = L.steps[n];
             a.obj = obj_params(c, n);
+            if (c->pv) {
+                a.Ps = reinterpret_cast<T *>(c->pv);
+                for (int k = 0; k < 3; ++k) a.Vs[k] = reinterpret_cast<T *>(c->field(c->pv, 1 + k));
+            }
             hipError_t e;
             {
                 Timed t(c, 1);
@@ -619,6 +624,7 @@ int create_impl(const lks_desc *d, lks_ctx *c) {
     ALLOC(kbar, L.b_kbar)
     ALLOC(adj, L.b_adj)
     ALLOC(fin, L.b_final)
+    ALLOC(pv, L.b_pv)
     ALLOC(gamma, L.nd * e)
     ALLOC(kref, L.nd * e)
     ALLOC(sens, L.nd * e)

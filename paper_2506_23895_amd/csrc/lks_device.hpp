@@ -272,24 +272,30 @@ __device__ __forceinline__ bool obj_uses_kappa(int kind) {
 }
 
 // ---- deterministic reductions ---------------------------------------------------------------
-// Sum over a 256-thread block in a fixed order; the result is valid on thread 0.
-__device__ __forceinline__ double block_sum(double v, double *sh4) {
+// Sum over a block of NT threads in a fixed order; the result is valid on thread 0.
+template <int NT>
+__device__ __forceinline__ double block_sum_t(double v, double *sh) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     __syncthreads();
-    if (lane == 0) sh4[w] = v;
+    if (lane == 0) sh[w] = v;
     __syncthreads();
     double t = 0.0;
-    if (threadIdx.x == 0) t = (sh4[0] + sh4[1]) + (sh4[2] + sh4[3]);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int i = 0; i < NT / 64; ++i) t += sh[i];
     return t;
 }
 
+__device__ __forceinline__ double block_sum(double v, double *sh4) { return block_sum_t<256>(v, sh4); }
+
 // Every block stores its partial for this step; the partials of all steps are summed in block
 // order by one reduction kernel at the end of the sweep (no cross-block synchronisation here).
+template <int NT = 256>
 __device__ __forceinline__ void store_partial(const ObjParams &o, double v, long long blin,
-                                              double *sh4) {
-    const double bs = block_sum(v, sh4);
+                                              double *sh) {
+    const double bs = block_sum_t<NT>(v, sh);
     if (threadIdx.x == 0) o.partials[blin] = bs;
 }
 

@@ -95,6 +95,8 @@ struct AdjArgs {
     BoxGeom box;
     StepMotion m;
     ObjParams obj;
+    T *Ps;              // 3D only: (P*, V*) scratch fields between the two adjoint kernels
+    T *Vs[3];
 };
 
 template <typename T>
@@ -141,7 +143,7 @@ hipError_t launch_reduce_steps(const double *partials, long long stride, long lo
                                int n1, double scale, double *jn, hipStream_t s);
 
 // grid sizes of the stencil launches (used by the host to size the partials buffer)
-long long fwd_blocks(const Geom &g, int lattice);
-long long adj_blocks(const Geom &g, int lattice);
+long long fwd_blocks(const Geom &g, int lattice, int esz);
+long long fwd_blocks3d(const Geom &g, int lattice, int esz);
 
 }  // namespace lks

@@ -355,12 +355,10 @@ hipError_t launch_adj2d(const AdjArgs<T> &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-long long fwd_blocks(const Geom &g, int lattice) {
-    (void)lattice;
+long long fwd_blocks(const Geom &g, int lattice, int esz) {
     if (g.dim == 2) return (long long)((g.n[0] + TX - 1) / TX) * ((g.n[1] + TY - 1) / TY);
-    return (long long)((g.n[0] + 31) / 32) * ((g.n[1] + 7) / 8) * ((g.n[2] + 7) / 8);
+    return fwd_blocks3d(g, lattice, esz);
 }
-long long adj_blocks(const Geom &g, int lattice) { return fwd_blocks(g, lattice); }
 
 template hipError_t launch_fwd2d<float>(const FwdArgs<float> &, hipStream_t);
 template hipError_t launch_fwd2d<double>(const FwdArgs<double> &, hipStream_t);

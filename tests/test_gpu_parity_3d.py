@@ -1,0 +1,79 @@
+"""GPU parity of the 3D D3Q19 / D3Q15 path against the FP64 CPU oracle (same tolerances as 2D)."""
+import math
+
+import numpy as np
+import pytest
+
+import lks_inputs as I
+from parity_util import announce, compare
+
+pytestmark = pytest.mark.gpu
+
+F64 = dict(tol_field=1e-11, tol_grad=1e-10, tol_J=1e-11)
+F32 = dict(tol_field=1e-4, tol_grad=1e-3, tol_J=1e-4)
+
+
+def _bc(kind, rho=1.0, u=(0.0, 0.0, 0.0)):
+    return {"kind": kind, "rho": rho, "u": u}
+
+
+def box3(n=(40, 19, 37), nd=(9, 8, 7), N=24, K=7, prec="F64", lattice="D3Q19", weight="LIN",
+         obj="TORQUE", bcs=None, motion="rotate", interp="FLUID_ONE", kmax=0.6):
+    centre = tuple((v - 1) / 2.0 for v in n)
+    centre = (centre[0] + 0.3, centre[1] - 0.2, centre[2] + 0.1)
+    if motion == "rotate":
+        mot = I.motion_rotation(N, centre, 2 * math.pi / 80)
+    else:
+        mot = I.motion_heave(N, centre, 1.5, 2 * math.pi / 40, theta_amp=0.3)
+    if bcs is None:
+        bcs = [_bc("VELOCITY", 1.0, (0.03, 0, 0)), _bc("ZERO_GRADIENT"), _bc("PERIODIC"),
+               _bc("PERIODIC"), _bc("PERIODIC"), _bc("PERIODIC")]
+    return I.make_config(dim=3, lattice=lattice, n=n, nd=nd, nu=0.05, nsteps=N, motion=mot,
+                         bcs=bcs, obj=I.objective(obj, 2, N, norm=1, centre=centre,
+                                                  direction=(0, 0, 1) if obj == "TORQUE" else (0.6, 0.0, 0.8)),
+                         u0=(0.03, 0, 0), weight=weight, interp=interp, kappa_max=kmax,
+                         precision=prec, checkpoint_every=K)
+
+
+CASES = {
+    "d3q19_channel_torque": dict(),
+    "d3q15_channel_torque": dict(lattice="D3Q15"),
+    "d3q19_walls_everywhere_power": dict(
+        obj="POWER", motion="heave",
+        bcs=[_bc("VELOCITY", 1.0, (0.03, 0, 0)), _bc("PRESSURE", 1.001, (0, 0.002, 0.001)),
+             _bc("NOSLIP"), _bc("NOSLIP", 1.0, (0.01, 0, 0)), _bc("ZERO_GRADIENT"), _bc("NOSLIP")]),
+    "d3q15_cos4_paper_drag": dict(lattice="D3Q15", weight="COS4", interp="PAPER", kmax=2.0,
+                                  obj="DRAG", n=(36, 34, 40), nd=(7, 7, 7)),
+    "d3q19_fully_periodic_j2": dict(obj="J2", bcs=I.periodic_bcs()),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_variants_fp64(name):
+    cfg = box3(**CASES[name])
+    announce(f"3d variant {name}")
+    g = I.gamma_field(cfg["nd"], 3, 7)
+    print(compare(cfg, g, check_ckpt=True, **F64))
+
+
+def test_d3q19_fp32():
+    cfg = box3(prec="F32", N=40, K=9)
+    announce("3d fp32")
+    g = I.gamma_field(cfg["nd"], 3, 8)
+    print(compare(cfg, g, **F32))
+
+
+def test_c4_copy48_fp32():
+    """Config-4 lattice parameters on a 48^3 copy (18^3 design, 240 steps, checkpoint every 50)."""
+    cfg = I.config_c4(n_side=48, nd_side=18, precision="F32", nsteps=240)
+    announce("c4 copy 48 fp32")
+    g = I.gamma_field(cfg["nd"], 3, 3)
+    print(compare(cfg, g, **F32))
+
+
+def test_c4_full_grid_short_fp32():
+    """The benchmark's 3D launch configuration (256^3 grid, 96^3 design) on 3 steps."""
+    cfg = I.config_c4(precision="F32", nsteps=3, checkpoint_every=2)
+    announce("c4 full grid 3 steps fp32")
+    g = I.gamma_field(cfg["nd"], 3, 3)
+    print(compare(cfg, g, **F32))
