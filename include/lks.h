@@ -179,6 +179,34 @@ int lks_read_objective_steps(lks_ctx *c, double *jn);
 int lks_set_timing(lks_ctx *c, int every);
 int lks_kernel_timing(lks_ctx *c, int kind, long *count, double *mean_ms);
 
+/* ---- continuous batching (the served path) ------------------------------------------------
+ * Many contexts advance together: each round moves every listed context by one micro-step of
+ * its evaluation (a forward step, a recomputed step, or an adjoint step with its sensitivity
+ * gather), and the kernels of all of them share one launch per kernel kind.  Every context of a
+ * round must use the batch's stream and one precision.  Results are bitwise identical to the
+ * single-context path: each job keeps its own buffers, tiles and fixed-order reductions. */
+typedef struct lks_batch lks_batch;
+
+/* Staging buffers for per-job kernel arguments (a ring of pinned slots) on stream. */
+int lks_batch_create(void *stream, lks_batch **out);
+void lks_batch_destroy(lks_batch *b);  /* NULL is a no-op; synchronises the stream */
+
+/* Start an evaluation of c (forward, reverse sweep, sensitivity) on device buffers: gamma is
+ * read and dJdgamma [nd] written in the context precision; both must stay valid until
+ * lks_finish returns.  Needs an io_on_device context with an objective.  Enqueues only. */
+int lks_begin(lks_ctx *c, const void *gamma, void *dJdgamma);
+
+/* One round over cs[0..n-1]; done[i] (optional) becomes 1 once the last kernel of context i's
+ * evaluation is enqueued.  Enqueues only (blocks only when the staging ring is full). */
+int lks_batch_round(lks_batch *b, lks_ctx *const *cs, int n, int *done);
+const char *lks_batch_error(const lks_batch *b);
+
+/* 1 if context c's evaluation has completed on the device, 0 if not yet (never blocks). */
+int lks_poll(lks_ctx *c);
+
+/* Wait for context c's evaluation and return J (host); dJdgamma is then complete. */
+int lks_finish(lks_ctx *c, double *J);
+
 /* Static description of the last failure of c (or of the last failed lks_create when c is
  * NULL), and of a return code. */
 const char *lks_last_error(const lks_ctx *c);

@@ -15,6 +15,9 @@
 #include "lks.h"
 #include "lks_internal.hpp"
 
+namespace lks {
+constexpr long long kBlockHost = 256;  // threads per block of the pointwise kernels
+}
 using lks::BoxGeom;
 using lks::Geom;
 using lks::StepMotion;
@@ -244,6 +247,15 @@ struct lks_ctx {
     double total_ms[3] = {0, 0, 0};
     std::vector<EventPair> pool;
     size_t pool_used = 0;
+    // continuous batching: where this context stands in its evaluation
+    struct Cursor {
+        int phase = 0;  // 0 idle, 1 forward, 2 reverse setup, 3 adjoint, 4 restore, 5 recompute, 6 done
+        int n = 0, seg = 0, cur = 0, acur = 0;
+    } cs;
+    double *jn_host = nullptr;  // pinned
+    int *flag_host = nullptr;   // pinned
+    void *out_dev = nullptr;    // caller's device buffer for dJ/dgamma
+    hipEvent_t done_ev = nullptr;
 
     size_t esz() const { return L.esz; }
     int D() const { return d.dim; }
@@ -346,8 +358,8 @@ struct Timed {
 };
 
 template <typename T>
-int launch_step_fwd(lks_ctx *c, int n, const T *rin, const T *const uin[3], T *rout,
-                    T *const uout[3], int box_slot, bool objective) {
+lks::FwdArgs<T> make_fwd_args(lks_ctx *c, int n, const T *rin, const T *const uin[3], T *rout,
+                              T *const uout[3], int box_slot, bool objective) {
     lks::FwdArgs<T> a{};
     a.g = c->L.g;
     a.bc = bc_params<T>(c->d);
@@ -370,6 +382,13 @@ int launch_step_fwd(lks_ctx *c, int n, const T *rin, const T *const uin[3], T *r
     }
     a.obj = obj_params(c, n);
     if (!objective) a.obj.active = 0;
+    return a;
+}
+
+template <typename T>
+int launch_step_fwd(lks_ctx *c, int n, const T *rin, const T *const uin[3], T *rout,
+                    T *const uout[3], int box_slot, bool objective) {
+    const lks::FwdArgs<T> a = make_fwd_args<T>(c, n, rin, uin, rout, uout, box_slot, objective);
     hipError_t e;
     {
         Timed t(c, 0);
@@ -505,6 +524,53 @@ int forward_impl(lks_ctx *c, const void *gamma, double *J) {
 }
 
 template <typename T>
+lks::AdjArgs<T> make_adj_args(lks_ctx *c, int n, int j, int acur) {
+    const Layout &L = c->L;
+    const int D = c->d.dim;
+    Fields<T> ad[2] = {state_fields<T>(c, c->adj), state_fields<T>(c, c->field(c->adj, 1 + D))};
+    lks::AdjArgs<T> a{};
+    a.g = L.g;
+    a.bc = bc_params<T>(c->d);
+    a.A = (T)(4.5 * (1.0 / 6.0 - c->d.nu));
+    a.Pin = ad[acur].r;
+    a.Pout = ad[1 - acur].r;
+    T *up[3], *uc[3];
+    traj_slot<T>(c, j - 1, up);
+    traj_slot<T>(c, j, uc);
+    for (int k = 0; k < 3; ++k) {
+        a.Vin[k] = ad[acur].u[k];
+        a.Vout[k] = ad[1 - acur].u[k];
+        a.uprev[k] = up[k];
+        a.ucur[k] = uc[k];
+    }
+    a.kstatic = reinterpret_cast<const T *>(c->kstatic);
+    const T *b = reinterpret_cast<const T *>(c->box) + (long long)(j - 1) * (1 + D) * L.box.cells;
+    a.kbox = b;
+    for (int k = 0; k < 3; ++k) a.usbox[k] = k < D ? b + (1 + k) * L.box.cells : nullptr;
+    a.kbar = reinterpret_cast<T *>(c->kbar);
+    a.box = L.box;
+    a.m = L.steps[n];
+    a.obj = obj_params(c, n);
+    if (c->pv) {
+        a.Ps = reinterpret_cast<T *>(c->pv);
+        for (int k = 0; k < 3; ++k) a.Vs[k] = reinterpret_cast<T *>(c->field(c->pv, 1 + k));
+    }
+    return a;
+}
+
+template <typename T>
+lks::SensArgs<T> make_sens_args(lks_ctx *c, int n) {
+    lks::SensArgs<T> sa{};
+    sa.kbar = reinterpret_cast<T *>(c->kbar);
+    sa.box = c->L.box;
+    sa.m = c->L.steps[n];
+    sa.des = design<T>(c);
+    sa.dim = c->d.dim;
+    sa.G = c->G;
+    return sa;
+}
+
+template <typename T>
 int adjoint_impl(lks_ctx *c) {
     const Layout &L = c->L;
     const int D = c->d.dim, N = c->d.nsteps, K = L.K, S = L.S;
@@ -535,46 +601,14 @@ int adjoint_impl(lks_ctx *c) {
         }
         for (int n = n1; n >= n0; --n) {
             const int j = n - seg * K;
-            lks::AdjArgs<T> a{};
-            a.g = L.g;
-            a.bc = bc_params<T>(c->d);
-            a.A = (T)(4.5 * (1.0 / 6.0 - c->d.nu));
-            a.Pin = ad[acur].r;
-            a.Pout = ad[1 - acur].r;
-            T *up[3], *uc[3];
-            traj_slot<T>(c, j - 1, up);
-            traj_slot<T>(c, j, uc);
-            for (int k = 0; k < 3; ++k) {
-                a.Vin[k] = ad[acur].u[k];
-                a.Vout[k] = ad[1 - acur].u[k];
-                a.uprev[k] = up[k];
-                a.ucur[k] = uc[k];
-            }
-            a.kstatic = reinterpret_cast<const T *>(c->kstatic);
-            const T *b = reinterpret_cast<const T *>(c->box) + (long long)(j - 1) * (1 + D) * L.box.cells;
-            a.kbox = b;
-            for (int k = 0; k < 3; ++k) a.usbox[k] = k < D ? b + (1 + k) * L.box.cells : nullptr;
-            a.kbar = reinterpret_cast<T *>(c->kbar);
-            a.box = L.box;
-            a.m = L.steps[n];
-            a.obj = obj_params(c, n);
-            if (c->pv) {
-                a.Ps = reinterpret_cast<T *>(c->pv);
-                for (int k = 0; k < 3; ++k) a.Vs[k] = reinterpret_cast<T *>(c->field(c->pv, 1 + k));
-            }
+            const lks::AdjArgs<T> a = make_adj_args<T>(c, n, j, acur);
             hipError_t e;
             {
                 Timed t(c, 1);
                 e = D == 2 ? lks::launch_adj2d<T>(a, c->stream) : lks::launch_adj3d<T>(a, c->d.lattice, c->stream);
             }
             HIPCHK(c, e);
-            lks::SensArgs<T> sa{};
-            sa.kbar = a.kbar;
-            sa.box = L.box;
-            sa.m = L.steps[n];
-            sa.des = design<T>(c);
-            sa.dim = D;
-            sa.G = c->G;
+            const lks::SensArgs<T> sa = make_sens_args<T>(c, n);
             {
                 Timed t(c, 2);
                 e = lks::launch_sens<T>(sa, c->stream);
@@ -680,6 +714,335 @@ int create_impl(const lks_desc *d, lks_ctx *c) {
     return LKS_OK;
 }
 
+}  // namespace
+
+// ================================ continuous batching ========================================
+// A batch advances many contexts by one micro-step each per round: one forward (or recompute)
+// step, or one adjoint step plus its sensitivity gather.  The kernels of every context in the
+// same micro-step kind share one launch over a (job, tile) list; per-job argument blocks are
+// staged through a ring of pinned buffers so the host can run ahead of the device.
+struct lks_batch {
+    hipStream_t stream = nullptr;
+    static constexpr int kSlots = 8;
+    static constexpr size_t kCap = 4u << 20;
+    char *host[kSlots] = {};
+    char *dev[kSlots] = {};
+    hipEvent_t ev[kSlots] = {};
+    bool used[kSlots] = {};
+    int next = 0;
+    long rounds = 0;
+    std::string err;
+};
+
+namespace {
+
+enum { PH_IDLE = 0, PH_FWD = 1, PH_ADJ_BEGIN = 2, PH_ADJ = 3, PH_REC_BEGIN = 4, PH_REC = 5, PH_DONE = 6 };
+
+template <typename T>
+struct RoundLists {
+    std::vector<lks::FwdArgs<T>> fwd[3];   // 2D, 3D D3Q19, 3D D3Q15
+    std::vector<long long> ftiles[3];
+    std::vector<lks::AdjArgs<T>> adj[3];
+    std::vector<long long> atiles[3], ablk[3];
+    std::vector<lks::SensArgs<T>> sens;
+    std::vector<long long> sblk;
+};
+
+int list_of(const lks_ctx *c) { return c->d.dim == 2 ? 0 : (c->d.lattice == LKS_D3Q19 ? 1 : 2); }
+
+long long tiles_of(const lks_ctx *c) {
+    return c->d.dim == 2 ? lks::tiles2d(c->L.g) : lks::tiles3d(c->L.g, (int)c->L.esz);
+}
+
+template <typename T>
+int begin_impl(lks_ctx *c, const void *gamma, void *out) {
+    const Layout &L = c->L;
+    const int D = c->d.dim;
+    c->have_fwd = c->have_adj = false;
+    HIPCHK(c, hipMemcpyAsync(c->gamma, gamma, L.nd * sizeof(T), hipMemcpyDefault, c->stream));
+    HIPCHK(c, lks::launch_design_prep<T>(reinterpret_cast<const T *>(c->gamma),
+                                         reinterpret_cast<T *>(c->kref), c->kprime, L.nd,
+                                         c->d.interp == LKS_INTERP_PAPER ? 0 : 1,
+                                         c->d.kappa_max, c->d.q, c->stream));
+    HIPCHK(c, lks::launch_fill<double>(c->jn, 0.0, c->d.nsteps + 1, c->stream));
+    Fields<T> st = state_fields<T>(c, c->state);
+    lks::InitArgs<T> ia{};
+    ia.g = L.g;
+    ia.bc = bc_params<T>(c->d);
+    ia.r0 = (T)(c->d.rho0 - 1.0);
+    for (int k = 0; k < 3; ++k) ia.u0[k] = k < D ? (T)c->d.u0[k] : T(0);
+    if (c->init) {
+        Fields<T> in = state_fields<T>(c, c->init);
+        ia.rinit = in.r;
+        for (int k = 0; k < 3; ++k) ia.uinit[k] = in.u[k];
+    }
+    ia.rout = st.r;
+    for (int k = 0; k < 3; ++k) ia.uout[k] = st.u[k];
+    HIPCHK(c, lks::launch_init<T>(ia, c->stream));
+    c->out_dev = out;
+    c->cs = lks_ctx::Cursor{};
+    c->cs.phase = PH_FWD;
+    c->cs.n = 1;
+    return LKS_OK;
+}
+
+// Enqueue this context's copies for its next micro-step and append its kernel arguments.
+// Returns 1 if the forward sweep ends with this step, 2 if the reverse sweep does, else 0.
+template <typename T>
+int plan_step(lks_ctx *c, RoundLists<T> &R, int *rc) {
+    const Layout &L = c->L;
+    const int D = c->d.dim, N = c->d.nsteps, K = L.K, S = L.S;
+    auto &cs = c->cs;
+    Fields<T> st[2] = {state_fields<T>(c, c->state), state_fields<T>(c, c->field(c->state, 1 + D))};
+    const int li = list_of(c);
+    auto seg_lo = [&](int sg) { return sg * K + 1; };
+    auto seg_hi = [&](int sg) { return std::min((sg + 1) * K, N); };
+    *rc = LKS_OK;
+    if (cs.phase == PH_FWD) {
+        const int n = cs.n, seg = (n - 1) / K, j = n - seg * K;
+        const bool last = seg == S - 1;
+        if (j == 1) {
+            T *ck = reinterpret_cast<T *>(c->field(c->ckpt, (long long)seg * (1 + D)));
+            if ((*rc = copy_fields<T>(c, ck, st[cs.cur].r, 1))) return 0;
+            if ((*rc = copy_fields<T>(c, ck + L.F, st[cs.cur].u[0], D))) return 0;
+            if (last) {
+                T *t0[3];
+                traj_slot<T>(c, 0, t0);
+                if ((*rc = copy_fields<T>(c, t0[0], st[cs.cur].u[0], D))) return 0;
+            }
+        }
+        T *uin[3], *uout[3];
+        if (last) {
+            traj_slot<T>(c, j - 1, uin);
+            traj_slot<T>(c, j, uout);
+        } else {
+            for (int k = 0; k < 3; ++k) {
+                uin[k] = st[cs.cur].u[k];
+                uout[k] = st[1 - cs.cur].u[k];
+            }
+        }
+        R.fwd[li].push_back(make_fwd_args<T>(c, n, st[cs.cur].r, uin, st[1 - cs.cur].r, uout,
+                                             last ? j - 1 : -1, true));
+        R.ftiles[li].push_back(tiles_of(c));
+        cs.cur = 1 - cs.cur;
+        cs.n = n + 1;
+        return cs.n > N ? 1 : 0;
+    }
+    if (cs.phase == PH_ADJ_BEGIN) {
+        Fields<T> ad = state_fields<T>(c, c->adj);
+        HIPCHK(c, lks::launch_fill<T>(ad.r, T(0), (long long)(1 + D) * L.F, c->stream));
+        HIPCHK(c, lks::launch_fill<double>(c->G, 0.0, L.nd, c->stream));
+        cs.seg = S - 1;
+        cs.n = seg_hi(cs.seg);
+        cs.acur = 0;
+        cs.phase = PH_ADJ;
+    }
+    if (cs.phase == PH_REC_BEGIN) {
+        const T *ck = reinterpret_cast<const T *>(c->field(c->ckpt, (long long)cs.seg * (1 + D)));
+        T *t0[3];
+        traj_slot<T>(c, 0, t0);
+        if ((*rc = copy_fields<T>(c, st[0].r, ck, 1))) return 0;
+        if ((*rc = copy_fields<T>(c, t0[0], ck + L.F, D))) return 0;
+        cs.cur = 0;
+        cs.n = seg_lo(cs.seg);
+        cs.phase = PH_REC;
+    }
+    if (cs.phase == PH_REC) {
+        const int n = cs.n, j = n - cs.seg * K;
+        T *uin[3], *uout[3];
+        traj_slot<T>(c, j - 1, uin);
+        traj_slot<T>(c, j, uout);
+        R.fwd[li].push_back(make_fwd_args<T>(c, n, st[cs.cur].r, uin, st[1 - cs.cur].r, uout, j - 1, false));
+        R.ftiles[li].push_back(tiles_of(c));
+        cs.cur = 1 - cs.cur;
+        cs.n = n + 1;
+        if (cs.n > seg_hi(cs.seg)) {
+            cs.phase = PH_ADJ;
+            cs.n = seg_hi(cs.seg);
+        }
+        return 0;
+    }
+    if (cs.phase == PH_ADJ) {
+        const int n = cs.n, j = n - cs.seg * K;
+        R.adj[li].push_back(make_adj_args<T>(c, n, j, cs.acur));
+        R.atiles[li].push_back(tiles_of(c));
+        R.ablk[li].push_back((L.ncell + lks::kBlockHost - 1) / lks::kBlockHost);
+        R.sens.push_back(make_sens_args<T>(c, n));
+        R.sblk.push_back((L.nd + lks::kBlockHost - 1) / lks::kBlockHost);
+        cs.acur = 1 - cs.acur;
+        cs.n = n - 1;
+        if (cs.n < seg_lo(cs.seg)) {
+            cs.seg -= 1;
+            if (cs.seg < 0) return 2;
+            cs.phase = PH_REC_BEGIN;
+        }
+        return 0;
+    }
+    return 0;
+}
+
+template <typename T>
+int end_forward(lks_ctx *c) {
+    const Layout &L = c->L;
+    const int D = c->d.dim, N = c->d.nsteps, K = L.K, S = L.S;
+    Fields<T> st = state_fields<T>(c, c->field(c->state, (long long)c->cs.cur * (1 + D)));
+    HIPCHK(c, lks::launch_reduce_steps(c->partials, L.max_blocks, L.max_blocks, c->d.objective.n0,
+                                       c->d.objective.n1, c->obj_scale, c->jn, c->stream));
+    Fields<T> fin = state_fields<T>(c, c->fin);
+    T *ul[3];
+    traj_slot<T>(c, N - (S - 1) * K, ul);
+    int rc;
+    if ((rc = copy_fields<T>(c, fin.r, st.r, 1))) return rc;
+    if ((rc = copy_fields<T>(c, fin.u[0], ul[0], D))) return rc;
+    HIPCHK(c, lks::launch_fill<int>(c->flag, 0, 1, c->stream));
+    HIPCHK(c, lks::launch_nonfinite<T>(fin.r, (long long)(1 + D) * L.F, c->flag, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->jn_host, c->jn, (N + 1) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->flag_host, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    c->cs.phase = PH_ADJ_BEGIN;
+    return LKS_OK;
+}
+
+template <typename T>
+int end_reverse(lks_ctx *c) {
+    HIPCHK(c, lks::launch_sens_finish<T>(c->kprime, c->G, reinterpret_cast<T *>(c->out_dev), c->L.nd, c->stream));
+    HIPCHK(c, hipEventRecord(c->done_ev, c->stream));
+    c->cs.phase = PH_DONE;
+    return LKS_OK;
+}
+
+size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+template <typename T>
+int round_impl(lks_batch *b, lks_ctx *const *cs, int n, int *done) {
+    RoundLists<T> R;
+    std::vector<int> ends(n, 0);
+    for (int i = 0; i < n; ++i) {
+        int rc = LKS_OK;
+        ends[i] = plan_step<T>(cs[i], R, &rc);
+        if (rc) {
+            b->err = cs[i]->err;
+            return rc;
+        }
+    }
+    // stage every argument list into one pinned slot and one device copy
+    const int sl = b->next;
+    b->next = (b->next + 1) % lks_batch::kSlots;
+    if (b->used[sl] && hipEventSynchronize(b->ev[sl]) != hipSuccess) {
+        b->err = "staging event failed";
+        return LKS_EDEVICE;
+    }
+    char *h = b->host[sl];
+    size_t off = 0;
+    auto put = [&](const void *src, size_t bytes) -> long long {
+        const size_t o = off;
+        if (off + align_up(bytes) > lks_batch::kCap) return -1;
+        if (bytes) std::memcpy(h + off, src, bytes);
+        off += align_up(bytes);
+        return (long long)o;
+    };
+    auto prefix = [](const std::vector<long long> &v, std::vector<long long> &p) {
+        p.resize(v.size());
+        long long acc = 0;
+        for (size_t i = 0; i < v.size(); ++i) {
+            p[i] = acc;
+            acc += v[i];
+        }
+        return acc;
+    };
+    struct Launch {
+        int kind, li;
+        long long args, t0, t1, total, total1;
+        int njobs;
+    };
+    std::vector<Launch> ls;
+    for (int li = 0; li < 3; ++li) {
+        if (!R.fwd[li].empty()) {
+            std::vector<long long> p;
+            const long long tot = prefix(R.ftiles[li], p);
+            Launch L{0, li, put(R.fwd[li].data(), R.fwd[li].size() * sizeof(lks::FwdArgs<T>)),
+                     put(p.data(), p.size() * 8), 0, tot, 0, (int)R.fwd[li].size()};
+            ls.push_back(L);
+        }
+        if (!R.adj[li].empty()) {
+            std::vector<long long> p, q;
+            const long long tot = prefix(R.atiles[li], p);
+            const long long totb = prefix(R.ablk[li], q);
+            Launch L{1, li, put(R.adj[li].data(), R.adj[li].size() * sizeof(lks::AdjArgs<T>)),
+                     put(p.data(), p.size() * 8), put(q.data(), q.size() * 8), tot, totb,
+                     (int)R.adj[li].size()};
+            ls.push_back(L);
+        }
+    }
+    if (!R.sens.empty()) {
+        std::vector<long long> p;
+        const long long tot = prefix(R.sblk, p);
+        Launch L{2, 0, put(R.sens.data(), R.sens.size() * sizeof(lks::SensArgs<T>)),
+                 put(p.data(), p.size() * 8), 0, tot, 0, (int)R.sens.size()};
+        ls.push_back(L);
+    }
+    for (const Launch &L : ls)
+        if (L.args < 0 || L.t0 < 0 || L.t1 < 0) {
+            b->err = "too many jobs in one round for the staging buffer";
+            return LKS_EINVAL;
+        }
+    if (off) {
+        hipError_t e = hipMemcpyAsync(b->dev[sl], h, off, hipMemcpyHostToDevice, b->stream);
+        if (e != hipSuccess) {
+            b->err = hipGetErrorString(e);
+            return LKS_EDEVICE;
+        }
+    }
+    char *dv = b->dev[sl];
+    for (const Launch &L : ls) {
+        hipError_t e = hipSuccess;
+        const auto *t0 = reinterpret_cast<const long long *>(dv + L.t0);
+        if (L.kind == 0) {
+            const auto *a = reinterpret_cast<const lks::FwdArgs<T> *>(dv + L.args);
+            e = L.li == 0 ? lks::launch_fwd2d_batch<T>(a, t0, L.njobs, L.total, b->stream)
+                          : lks::launch_fwd3d_batch<T>(a, t0, L.njobs, L.total, L.li == 1 ? LKS_D3Q19 : LKS_D3Q15, b->stream);
+        } else if (L.kind == 1) {
+            const auto *a = reinterpret_cast<const lks::AdjArgs<T> *>(dv + L.args);
+            e = L.li == 0 ? lks::launch_adj2d_batch<T>(a, t0, L.njobs, L.total, b->stream)
+                          : lks::launch_adj3d_batch<T>(a, reinterpret_cast<const long long *>(dv + L.t1), L.total1,
+                                                       t0, L.total, L.njobs, L.li == 1 ? LKS_D3Q19 : LKS_D3Q15, b->stream);
+        }
+        if (e != hipSuccess) {
+            b->err = hipGetErrorString(e);
+            return LKS_EDEVICE;
+        }
+    }
+    for (const Launch &L : ls) {  // sensitivity gathers after every adjoint step of the round
+        if (L.kind != 2) continue;
+        hipError_t e = lks::launch_sens_batch<T>(reinterpret_cast<const lks::SensArgs<T> *>(dv + L.args),
+                                                 reinterpret_cast<const long long *>(dv + L.t0), L.njobs,
+                                                 L.total, b->stream);
+        if (e != hipSuccess) {
+            b->err = hipGetErrorString(e);
+            return LKS_EDEVICE;
+        }
+    }
+    if (hipEventRecord(b->ev[sl], b->stream) != hipSuccess) {
+        b->err = "event record failed";
+        return LKS_EDEVICE;
+    }
+    b->used[sl] = true;
+    for (int i = 0; i < n; ++i) {
+        int rc = LKS_OK;
+        if (ends[i] == 1) rc = end_forward<T>(cs[i]);
+        else if (ends[i] == 2) rc = end_reverse<T>(cs[i]);
+        if (rc) {
+            b->err = cs[i]->err;
+            return rc;
+        }
+        if (done) done[i] = cs[i]->cs.phase == PH_DONE;
+    }
+    b->rounds++;
+    return LKS_OK;
+}
+
+}  // namespace
+
+namespace {
 int set_err(lks_ctx *c, int code, const char *msg) {
     if (c) c->err = msg;
     return code;
@@ -737,6 +1100,9 @@ void lks_destroy(lks_ctx *c) {
         if (ev.a) (void)hipEventDestroy(ev.a);
         if (ev.b) (void)hipEventDestroy(ev.b);
     }
+    if (c->done_ev) (void)hipEventDestroy(c->done_ev);
+    if (c->jn_host) (void)hipHostFree(c->jn_host);
+    if (c->flag_host) (void)hipHostFree(c->flag_host);
     delete c;
 }
 
@@ -832,6 +1198,105 @@ int lks_kernel_timing(lks_ctx *c, int kind, long *count, double *mean_ms) {
     if (count) *count = c->samples[kind];
     if (mean_ms) *mean_ms = c->samples[kind] ? c->total_ms[kind] / c->samples[kind] : 0.0;
     (void)kind_name;
+    return LKS_OK;
+}
+
+int lks_batch_create(void *stream, lks_batch **out) {
+    if (!out) return LKS_EINVAL;
+    *out = nullptr;
+    lks_batch *b = new (std::nothrow) lks_batch();
+    if (!b) return LKS_ENOMEM;
+    b->stream = reinterpret_cast<hipStream_t>(stream);
+    for (int i = 0; i < lks_batch::kSlots; ++i) {
+        if (hipHostMalloc(reinterpret_cast<void **>(&b->host[i]), lks_batch::kCap, 0) != hipSuccess ||
+            hipMalloc(reinterpret_cast<void **>(&b->dev[i]), lks_batch::kCap) != hipSuccess ||
+            hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming) != hipSuccess) {
+            g_create_error = "batch staging allocation failed";
+            lks_batch_destroy(b);
+            return LKS_ENOMEM;
+        }
+    }
+    *out = b;
+    return LKS_OK;
+}
+
+void lks_batch_destroy(lks_batch *b) {
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    for (int i = 0; i < lks_batch::kSlots; ++i) {
+        if (b->host[i]) (void)hipHostFree(b->host[i]);
+        if (b->dev[i]) (void)hipFree(b->dev[i]);
+        if (b->ev[i]) (void)hipEventDestroy(b->ev[i]);
+    }
+    delete b;
+}
+
+int lks_begin(lks_ctx *c, const void *gamma, void *dJdgamma) {
+    if (!c) return LKS_EINVAL;
+    if (!gamma || !dJdgamma) return set_err(c, LKS_EINVAL, "gamma and dJdgamma are required");
+    if (!c->d.io_on_device) return set_err(c, LKS_EINVAL, "lks_begin needs an io_on_device context");
+    if (c->L.fwd_only) return set_err(c, LKS_ESTATE, "the objective is NONE: nothing to differentiate");
+    if (c->cs.phase != 0 && c->cs.phase != 6) return set_err(c, LKS_ESTATE, "an evaluation is in flight");
+    if (!c->jn_host) {
+        if (hipHostMalloc(reinterpret_cast<void **>(&c->jn_host), (c->d.nsteps + 1) * sizeof(double), 0) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void **>(&c->flag_host), sizeof(int), 0) != hipSuccess ||
+            hipEventCreateWithFlags(&c->done_ev, hipEventDisableTiming) != hipSuccess)
+            return set_err(c, LKS_ENOMEM, "pinned host allocation failed");
+    }
+    try {
+        return c->L.esz == 8 ? begin_impl<double>(c, gamma, dJdgamma) : begin_impl<float>(c, gamma, dJdgamma);
+    } catch (...) {
+        return set_err(c, LKS_ENOMEM, "host exception in lks_begin");
+    }
+}
+
+int lks_batch_round(lks_batch *b, lks_ctx *const *cs, int n, int *done) {
+    if (!b || (n > 0 && !cs)) return LKS_EINVAL;
+    if (n == 0) return LKS_OK;
+    const size_t esz = cs[0]->L.esz;
+    for (int i = 0; i < n; ++i) {
+        if (!cs[i] || cs[i]->L.esz != esz || cs[i]->stream != b->stream) {
+            b->err = "every context of a round needs the batch stream and the same precision";
+            return LKS_EINVAL;
+        }
+        if (cs[i]->cs.phase == 0) {
+            b->err = "context has no evaluation in flight (call lks_begin)";
+            return LKS_ESTATE;
+        }
+    }
+    try {
+        return esz == 8 ? round_impl<double>(b, cs, n, done) : round_impl<float>(b, cs, n, done);
+    } catch (...) {
+        b->err = "host exception in lks_batch_round";
+        return LKS_ENOMEM;
+    }
+}
+
+const char *lks_batch_error(const lks_batch *b) { return b ? b->err.c_str() : "NULL batch"; }
+
+int lks_poll(lks_ctx *c) {
+    if (!c) return LKS_EINVAL;
+    if (c->cs.phase != 6) return 0;
+    const hipError_t e = hipEventQuery(c->done_ev);
+    if (e == hipSuccess) return 1;
+    if (e == hipErrorNotReady) return 0;
+    c->err = hipGetErrorString(e);
+    return LKS_EDEVICE;
+}
+
+int lks_finish(lks_ctx *c, double *J) {
+    if (!c) return LKS_EINVAL;
+    if (c->cs.phase != 6) return set_err(c, LKS_ESTATE, "evaluation not finished");
+    HIPCHK(c, hipEventSynchronize(c->done_ev));
+    double acc = 0.0;
+    for (int n = 0; n <= c->d.nsteps; ++n) acc += c->jn_host[n];
+    if (J) *J = acc;
+    c->cs.phase = 0;
+    if (*c->flag_host) {
+        c->err = "non-finite value in the final state";
+        return LKS_ENONFINITE;
+    }
+    c->have_fwd = c->have_adj = true;
     return LKS_OK;
 }
 

@@ -142,6 +142,26 @@ hipError_t launch_nonfinite(const T *p, long long count, int *flag, hipStream_t 
 hipError_t launch_reduce_steps(const double *partials, long long stride, long long nblocks, int n0,
                                int n1, double scale, double *jn, hipStream_t s);
 
+// batched launches: job j owns flat blocks [tile0[j], tile0[j+1]) (tile0 ascending from 0)
+template <typename T>
+hipError_t launch_fwd2d_batch(const FwdArgs<T> *args, const long long *tile0, int njobs,
+                              long long ntiles, hipStream_t s);
+template <typename T>
+hipError_t launch_adj2d_batch(const AdjArgs<T> *args, const long long *tile0, int njobs,
+                              long long ntiles, hipStream_t s);
+template <typename T>
+hipError_t launch_fwd3d_batch(const FwdArgs<T> *args, const long long *tile0, int njobs,
+                              long long ntiles, int lattice, hipStream_t s);
+template <typename T>
+hipError_t launch_adj3d_batch(const AdjArgs<T> *args, const long long *blk0, long long nblk,
+                              const long long *tile0, long long ntiles, int njobs, int lattice,
+                              hipStream_t s);
+template <typename T>
+hipError_t launch_sens_batch(const SensArgs<T> *args, const long long *blk0, int njobs, long long nblk,
+                             hipStream_t s);
+long long tiles2d(const Geom &g);
+long long tiles3d(const Geom &g, int esz);
+
 // grid sizes of the stencil launches (used by the host to size the partials buffer)
 long long fwd_blocks(const Geom &g, int lattice, int esz);
 long long fwd_blocks3d(const Geom &g, int lattice, int esz);

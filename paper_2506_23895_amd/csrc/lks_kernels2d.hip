@@ -32,7 +32,7 @@ __device__ constexpr double wt(int i) { return i == 0 ? W0 : (i < 5 ? WA : WD); 
 constexpr int TX = 64, TY = 8;
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_fwd2d(const FwdArgs<T> a) {
+__device__ __forceinline__ void fwd2d_body(const FwdArgs<T> &a, int bx, int by, long long blin) {
     constexpr int UX = TX + 4, UY = TY + 4;  // u staged with halo 2, origin (x0-2, y0-2)
     constexpr int EX = TX + 2, EY = TY + 2;  // rho and E_i with halo 1, origin (x0-1, y0-1)
     __shared__ T su[2][UY][UX];
@@ -41,7 +41,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd2d(const FwdArgs<T> a) {
     __shared__ double sh4[4];
 
     const int tid = threadIdx.x;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    const int x0 = bx * TX, y0 = by * TY;
     const Geom &g = a.g;
     const int nx = g.n[0], ny = g.n[1];
 
@@ -161,7 +161,35 @@ __global__ __launch_bounds__(kBlock) void k_fwd2d(const FwdArgs<T> a) {
             }
         });
     }
-    if (obj_on) store_partial(a.obj, jacc, blockIdx.x + (long long)blockIdx.y * gridDim.x, sh4);
+    if (obj_on) store_partial(a.obj, jacc, blin, sh4);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fwd2d(const FwdArgs<T> a) {
+    fwd2d_body<T>(a, blockIdx.x, blockIdx.y, blockIdx.x + (long long)blockIdx.y * gridDim.x);
+}
+
+// first tile of the job that owns flat tile b (tile0 ascending, tile0[0] = 0)
+__device__ __forceinline__ int job_of(const long long *tile0, int njobs, long long b) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tile0[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// one launch for the current step of many jobs: flat tile b -> (job, local tile)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fwd2d_batch(const FwdArgs<T> *args, const long long *tile0,
+                                                        int njobs) {
+    const long long b = blockIdx.x;
+    const int j = job_of(tile0, njobs, b);
+    const FwdArgs<T> &a = args[j];
+    const long long t = b - tile0[j];
+    const int nbx = (a.g.n[0] + TX - 1) / TX;
+    fwd2d_body<T>(a, (int)(t % nbx), (int)(t / nbx), t);
 }
 
 // transposed difference operator along one axis at coordinate c: sum_r D[r][c] f(r), with f
@@ -184,7 +212,7 @@ __device__ __forceinline__ T deriv_T(const T f[5], int c, int n, int per) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_adj2d(const AdjArgs<T> a) {
+__device__ __forceinline__ void adj2d_body(const AdjArgs<T> &a, int bx, int by) {
     constexpr int LX = TX + 8, LY = TY + 8;  // lambda, halo 4, origin (x0-4, y0-4)
     constexpr int PX = TX + 6, PY = TY + 6;  // P*, V*, halo 3, origin (x0-3, y0-3)
     constexpr int MX = TX + 4, MY = TY + 4;  // moments, halo 2, origin (x0-2, y0-2)
@@ -193,7 +221,7 @@ __global__ __launch_bounds__(kBlock) void k_adj2d(const AdjArgs<T> a) {
     __shared__ T sPV[3][PY][PX];
 
     const int tid = threadIdx.x;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    const int x0 = bx * TX, y0 = by * TY;
     const Geom &g = a.g;
     const int nx = g.n[0], ny = g.n[1];
     const bool obj_on = a.obj.active && a.obj.kind != OBJ_NONE;
@@ -342,6 +370,22 @@ __global__ __launch_bounds__(kBlock) void k_adj2d(const AdjArgs<T> a) {
 }
 
 template <typename T>
+__global__ __launch_bounds__(kBlock) void k_adj2d(const AdjArgs<T> a) {
+    adj2d_body<T>(a, blockIdx.x, blockIdx.y);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_adj2d_batch(const AdjArgs<T> *args, const long long *tile0,
+                                                        int njobs) {
+    const long long b = blockIdx.x;
+    const int j = job_of(tile0, njobs, b);
+    const AdjArgs<T> &a = args[j];
+    const long long t = b - tile0[j];
+    const int nbx = (a.g.n[0] + TX - 1) / TX;
+    adj2d_body<T>(a, (int)(t % nbx), (int)(t / nbx));
+}
+
+template <typename T>
 hipError_t launch_fwd2d(const FwdArgs<T> &a, hipStream_t s) {
     dim3 grid((a.g.n[0] + TX - 1) / TX, (a.g.n[1] + TY - 1) / TY);
     hipLaunchKernelGGL(k_fwd2d<T>, grid, dim3(kBlock), 0, s, a);
@@ -359,6 +403,27 @@ long long fwd_blocks(const Geom &g, int lattice, int esz) {
     if (g.dim == 2) return (long long)((g.n[0] + TX - 1) / TX) * ((g.n[1] + TY - 1) / TY);
     return fwd_blocks3d(g, lattice, esz);
 }
+
+long long tiles2d(const Geom &g) { return (long long)((g.n[0] + TX - 1) / TX) * ((g.n[1] + TY - 1) / TY); }
+
+template <typename T>
+hipError_t launch_fwd2d_batch(const FwdArgs<T> *args, const long long *tile0, int njobs,
+                              long long ntiles, hipStream_t s) {
+    if (njobs == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fwd2d_batch<T>, dim3((unsigned)ntiles), dim3(kBlock), 0, s, args, tile0, njobs);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_adj2d_batch(const AdjArgs<T> *args, const long long *tile0, int njobs,
+                              long long ntiles, hipStream_t s) {
+    if (njobs == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adj2d_batch<T>, dim3((unsigned)ntiles), dim3(kBlock), 0, s, args, tile0, njobs);
+    return hipGetLastError();
+}
+template hipError_t launch_fwd2d_batch<float>(const FwdArgs<float> *, const long long *, int, long long, hipStream_t);
+template hipError_t launch_fwd2d_batch<double>(const FwdArgs<double> *, const long long *, int, long long, hipStream_t);
+template hipError_t launch_adj2d_batch<float>(const AdjArgs<float> *, const long long *, int, long long, hipStream_t);
+template hipError_t launch_adj2d_batch<double>(const AdjArgs<double> *, const long long *, int, long long, hipStream_t);
 
 template hipError_t launch_fwd2d<float>(const FwdArgs<float> &, hipStream_t);
 template hipError_t launch_fwd2d<double>(const FwdArgs<double> &, hipStream_t);

@@ -67,7 +67,7 @@ __device__ __forceinline__ T dcoord(T fm2, T fm1, T f0, T fp1, T fp2, int c, int
 
 // ================================== forward ==================================================
 template <typename T, int Q>
-__global__ __launch_bounds__(Tile3<T>::TX * Tile3<T>::TY) void k_fwd3d(const FwdArgs<T> a) {
+__device__ __forceinline__ void fwd3d_body(const FwdArgs<T> &a, int bx, int by, int bz, long long blin) {
     constexpr int TX = Tile3<T>::TX, TY = Tile3<T>::TY, ZC = Tile3<T>::ZC, NT = TX * TY;
     constexpr int UX = TX + 4, UY = TY + 4, UP = UX * UY;  // velocity plane, halo 2
     constexpr int EX = TX + 2, EY = TY + 2, EP = EX * EY;  // E_i plane, halo 1
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(Tile3<T>::TX * Tile3<T>::TY) void k_fwd3d(const Fwd
     const Geom &g = a.g;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     const int tid = threadIdx.x;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, zs = blockIdx.z * ZC;
+    const int x0 = bx * TX, y0 = by * TY, zs = bz * ZC;
     const int ze = min(zs + ZC, nz);
     const int ox = tid % TX, oy = tid / TX;
     const T A = a.A;
@@ -258,10 +258,45 @@ __global__ __launch_bounds__(Tile3<T>::TX * Tile3<T>::TY) void k_fwd3d(const Fwd
         }
         __syncthreads();
     }
-    if (obj_on)
-        store_partial<NT>(a.obj, jacc,
-                          blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z),
-                          sh);
+    if (obj_on) store_partial<NT>(a.obj, jacc, blin, sh);
+}
+
+template <typename T, int Q>
+__global__ __launch_bounds__(Tile3<T>::TX * Tile3<T>::TY) void k_fwd3d(const FwdArgs<T> a) {
+    fwd3d_body<T, Q>(a, blockIdx.x, blockIdx.y, blockIdx.z,
+                     blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z));
+}
+
+__device__ __forceinline__ int job_of3(const long long *tile0, int njobs, long long b) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tile0[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename T>
+__device__ __forceinline__ void tile_coords3(const Geom &g, long long t, int &bx, int &by, int &bz) {
+    const int nbx = (g.n[0] + Tile3<T>::TX - 1) / Tile3<T>::TX;
+    const int nby = (g.n[1] + Tile3<T>::TY - 1) / Tile3<T>::TY;
+    bx = (int)(t % nbx);
+    by = (int)((t / nbx) % nby);
+    bz = (int)(t / ((long long)nbx * nby));
+}
+
+template <typename T, int Q>
+__global__ __launch_bounds__(Tile3<T>::TX * Tile3<T>::TY) void k_fwd3d_batch(const FwdArgs<T> *args,
+                                                                            const long long *tile0,
+                                                                            int njobs) {
+    const long long b = blockIdx.x;
+    const int j = job_of3(tile0, njobs, b);
+    const FwdArgs<T> &a = args[j];
+    const long long t = b - tile0[j];
+    int bx, by, bz;
+    tile_coords3<T>(a.g, t, bx, by, bz);
+    fwd3d_body<T, Q>(a, bx, by, bz, t);
 }
 
 // ================================== adjoint, pointwise part ===================================
@@ -293,10 +328,10 @@ __device__ __forceinline__ void lambda_at(const AdjArgs<T> &a, int x, int y, int
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_adj3d_prep(const AdjArgs<T> a) {
+__device__ __forceinline__ void adj3d_prep_body(const AdjArgs<T> &a, long long blk) {
     const Geom &g = a.g;
     const long long ncell = (long long)g.n[0] * g.n[1] * g.n[2];
-    const long long t = blockIdx.x * (long long)kBlock + threadIdx.x;
+    const long long t = blk * kBlock + threadIdx.x;
     if (t >= ncell) return;
     const int x = (int)(t % g.n[0]);
     const int y = (int)((t / g.n[0]) % g.n[1]);
@@ -347,6 +382,19 @@ __global__ __launch_bounds__(kBlock) void k_adj3d_prep(const AdjArgs<T> a) {
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_adj3d_prep(const AdjArgs<T> a) {
+    adj3d_prep_body<T>(a, blockIdx.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_adj3d_prep_batch(const AdjArgs<T> *args,
+                                                             const long long *blk0, int njobs) {
+    const long long b = blockIdx.x;
+    const int j = job_of3(blk0, njobs, b);
+    adj3d_prep_body<T>(args[j], b - blk0[j]);
+}
+
 // ================================== adjoint, z-marching part ==================================
 template <typename T>
 __device__ __forceinline__ T deriv_T3(const T f[5], int c, int n, int per) {
@@ -366,7 +414,7 @@ __device__ __forceinline__ T deriv_T3(const T f[5], int c, int n, int per) {
 }
 
 template <typename T, int Q>
-__global__ __launch_bounds__(Tile3<T>::TX * Tile3<T>::TY) void k_adj3d_main(const AdjArgs<T> a) {
+__device__ __forceinline__ void adj3d_main_body(const AdjArgs<T> &a, int bx, int by, int bz) {
     constexpr int TX = Tile3<T>::TX, TY = Tile3<T>::TY, ZC = Tile3<T>::ZC, NT = TX * TY;
     constexpr int PX = TX + 6, PY = TY + 6, PP = PX * PY;  // (P*, V*) plane, halo 3
     constexpr int MX = TX + 4, MY = TY + 4, MP = MX * MY;  // moment plane, halo 2
@@ -379,7 +427,7 @@ __global__ __launch_bounds__(Tile3<T>::TX * Tile3<T>::TY) void k_adj3d_main(cons
     const Geom &g = a.g;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     const int tid = threadIdx.x;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, zs = blockIdx.z * ZC;
+    const int x0 = bx * TX, y0 = by * TY, zs = bz * ZC;
     const int ze = min(zs + ZC, nz);
     const int ox = tid % TX, oy = tid / TX;
 
@@ -534,6 +582,23 @@ __global__ __launch_bounds__(Tile3<T>::TX * Tile3<T>::TY) void k_adj3d_main(cons
     }
 }
 
+template <typename T, int Q>
+__global__ __launch_bounds__(Tile3<T>::TX * Tile3<T>::TY) void k_adj3d_main(const AdjArgs<T> a) {
+    adj3d_main_body<T, Q>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+template <typename T, int Q>
+__global__ __launch_bounds__(Tile3<T>::TX * Tile3<T>::TY) void k_adj3d_main_batch(const AdjArgs<T> *args,
+                                                                                 const long long *tile0,
+                                                                                 int njobs) {
+    const long long b = blockIdx.x;
+    const int j = job_of3(tile0, njobs, b);
+    const AdjArgs<T> &a = args[j];
+    int bx, by, bz;
+    tile_coords3<T>(a.g, b - tile0[j], bx, by, bz);
+    adj3d_main_body<T, Q>(a, bx, by, bz);
+}
+
 long long fwd_blocks3d(const Geom &g, int lattice, int esz) {
     (void)lattice;
     const int TX = esz == 8 ? Tile3<double>::TX : Tile3<float>::TX;
@@ -566,6 +631,39 @@ hipError_t launch_adj3d(const AdjArgs<T> &a, int lattice, hipStream_t s) {
     else hipLaunchKernelGGL((k_adj3d_main<T, 15>), grid3<T>(a.g), blk, 0, s, a);
     return hipGetLastError();
 }
+
+long long tiles3d(const Geom &g, int esz) { return fwd_blocks3d(g, 0, esz); }
+
+template <typename T>
+hipError_t launch_fwd3d_batch(const FwdArgs<T> *args, const long long *tile0, int njobs,
+                              long long ntiles, int lattice, hipStream_t s) {
+    if (njobs == 0) return hipSuccess;
+    const dim3 blk(Tile3<T>::TX * Tile3<T>::TY);
+    if (lattice == 2) hipLaunchKernelGGL((k_fwd3d_batch<T, 19>), dim3((unsigned)ntiles), blk, 0, s, args, tile0, njobs);
+    else hipLaunchKernelGGL((k_fwd3d_batch<T, 15>), dim3((unsigned)ntiles), blk, 0, s, args, tile0, njobs);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adj3d_batch(const AdjArgs<T> *args, const long long *blk0, long long nblk,
+                              const long long *tile0, long long ntiles, int njobs, int lattice,
+                              hipStream_t s) {
+    if (njobs == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adj3d_prep_batch<T>, dim3((unsigned)nblk), dim3(kBlock), 0, s, args, blk0, njobs);
+    const dim3 blk(Tile3<T>::TX * Tile3<T>::TY);
+    if (lattice == 2) hipLaunchKernelGGL((k_adj3d_main_batch<T, 19>), dim3((unsigned)ntiles), blk, 0, s, args, tile0, njobs);
+    else hipLaunchKernelGGL((k_adj3d_main_batch<T, 15>), dim3((unsigned)ntiles), blk, 0, s, args, tile0, njobs);
+    return hipGetLastError();
+}
+
+#define LKS_INST3(T)                                                                                  \
+    template hipError_t launch_fwd3d_batch<T>(const FwdArgs<T> *, const long long *, int, long long,  \
+                                              int, hipStream_t);                                      \
+    template hipError_t launch_adj3d_batch<T>(const AdjArgs<T> *, const long long *, long long,       \
+                                              const long long *, long long, int, int, hipStream_t);
+LKS_INST3(float)
+LKS_INST3(double)
+#undef LKS_INST3
 
 template hipError_t launch_fwd3d<float>(const FwdArgs<float> &, int, hipStream_t);
 template hipError_t launch_fwd3d<double>(const FwdArgs<double> &, int, hipStream_t);

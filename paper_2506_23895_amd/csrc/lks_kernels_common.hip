@@ -52,9 +52,9 @@ __global__ __launch_bounds__(kBlock) void k_init(const InitArgs<T> a) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_sens(const SensArgs<T> a) {
+__device__ __forceinline__ void sens_body(const SensArgs<T> &a, long long blk) {
     const long long ndn = (long long)a.des.nd[0] * a.des.nd[1] * a.des.nd[2];
-    const long long i = blockIdx.x * (long long)kBlock + threadIdx.x;
+    const long long i = blk * kBlock + threadIdx.x;
     if (i >= ndn) return;
     const int ix = (int)(i % a.des.nd[0]);
     const int iy = (int)((i / a.des.nd[0]) % a.des.nd[1]);
@@ -86,6 +86,24 @@ __global__ __launch_bounds__(kBlock) void k_sens(const SensArgs<T> a) {
         }
     }
     a.G[i] += acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_sens(const SensArgs<T> a) {
+    sens_body<T>(a, blockIdx.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_sens_batch(const SensArgs<T> *args, const long long *blk0,
+                                                       int njobs) {
+    const long long b = blockIdx.x;
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (blk0[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    sens_body<T>(args[lo], b - blk0[lo]);
 }
 
 template <typename T>
@@ -144,6 +162,14 @@ hipError_t launch_sens(const SensArgs<T> &a, hipStream_t s) {
 }
 
 template <typename T>
+hipError_t launch_sens_batch(const SensArgs<T> *args, const long long *blk0, int njobs, long long nblk,
+                             hipStream_t s) {
+    if (njobs == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sens_batch<T>, dim3((unsigned)nblk), dim3(kBlock), 0, s, args, blk0, njobs);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_sens_finish(const double *kprime, const double *G, T *out, long long nd,
                               hipStream_t s) {
     hipLaunchKernelGGL(k_sens_finish<T>, grid1(nd), dim3(kBlock), 0, s, kprime, G, out, nd);
@@ -177,6 +203,8 @@ hipError_t launch_reduce_steps(const double *partials, long long stride, long lo
                                               double, hipStream_t);                               \
     template hipError_t launch_init<T>(const InitArgs<T> &, hipStream_t);                         \
     template hipError_t launch_sens<T>(const SensArgs<T> &, hipStream_t);                         \
+    template hipError_t launch_sens_batch<T>(const SensArgs<T> *, const long long *, int, long long, \
+                                             hipStream_t);                                        \
     template hipError_t launch_sens_finish<T>(const double *, const double *, T *, long long,     \
                                               hipStream_t);                                       \
     template hipError_t launch_fill<T>(T *, T, long long, hipStream_t);                           \

@@ -32,7 +32,9 @@ _PREC = {"F32": 0, "F64": 1}
 
 EXPORTS = ["lks_query_bytes", "lks_create", "lks_destroy", "lks_forward", "lks_adjoint",
            "lks_sensitivity", "lks_read_state", "lks_read_objective_steps", "lks_set_timing",
-           "lks_kernel_timing", "lks_last_error", "lks_strerror"]
+           "lks_kernel_timing", "lks_last_error", "lks_strerror", "lks_batch_create",
+           "lks_batch_destroy", "lks_begin", "lks_batch_round", "lks_batch_error", "lks_poll",
+           "lks_finish"]
 
 
 class LksBc(C.Structure):
@@ -101,6 +103,15 @@ def lib():
         L.lks_last_error.restype = C.c_char_p
         L.lks_strerror.argtypes = [C.c_int]
         L.lks_strerror.restype = C.c_char_p
+        L.lks_batch_create.argtypes = [P, C.POINTER(P)]
+        L.lks_batch_destroy.argtypes = [P]
+        L.lks_batch_destroy.restype = None
+        L.lks_begin.argtypes = [P, P, P]
+        L.lks_batch_round.argtypes = [P, C.POINTER(P), C.c_int, C.POINTER(C.c_int)]
+        L.lks_batch_error.argtypes = [P]
+        L.lks_batch_error.restype = C.c_char_p
+        L.lks_poll.argtypes = [P]
+        L.lks_finish.argtypes = [P, C.POINTER(C.c_double)]
         _lib = L
     return _lib
 
@@ -252,6 +263,25 @@ class Solver:
         _check(lib().lks_kernel_timing(self._ctx, kind, C.byref(cnt), C.byref(ms)), self._ctx)
         return int(cnt.value), float(ms.value)
 
+    # -- continuous batching (device IO) -----------------------------------------------------
+    def begin(self, gamma, out) -> None:
+        """Start an evaluation whose kernels run in Batch.round() calls; keep gamma/out alive."""
+        self._begun = (gamma, out)
+        _check(lib().lks_begin(self._ctx, C.c_void_p(int(gamma.data_ptr())),
+                               C.c_void_p(int(out.data_ptr()))), self._ctx)
+
+    def poll(self) -> bool:
+        rc = lib().lks_poll(self._ctx)
+        if rc < 0:
+            _check(rc, self._ctx)
+        return rc == 1
+
+    def finish(self) -> float:
+        J = C.c_double(0.0)
+        _check(lib().lks_finish(self._ctx, C.byref(J)), self._ctx)
+        self._begun = None
+        return J.value
+
     def close(self) -> None:
         if self._ctx:
             lib().lks_destroy(self._ctx)
@@ -268,3 +298,31 @@ class Solver:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class Batch:
+    """lks_batch: advance many contexts one micro-step per round with shared kernel launches."""
+
+    def __init__(self, stream: Optional[int] = None):
+        self._b = C.c_void_p(None)
+        _check(lib().lks_batch_create(stream, C.byref(self._b)))
+
+    def round(self, solvers) -> np.ndarray:
+        n = len(solvers)
+        arr = (C.c_void_p * n)(*[s._ctx for s in solvers])
+        done = (C.c_int * n)()
+        rc = lib().lks_batch_round(self._b, arr, n, done)
+        if rc != LKS_OK:
+            raise LksError(rc, lib().lks_batch_error(self._b).decode())
+        return np.frombuffer(done, dtype=np.int32).copy()
+
+    def close(self) -> None:
+        if self._b:
+            lib().lks_batch_destroy(self._b)
+            self._b = C.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
