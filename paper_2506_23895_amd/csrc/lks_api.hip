@@ -49,7 +49,7 @@ struct Layout {
     size_t bytes = 0;
     // byte sizes of each allocation
     size_t b_state = 0, b_ckpt = 0, b_traj = 0, b_box = 0, b_kbar = 0, b_adj = 0, b_design = 0,
-           b_aux = 0, b_final = 0, b_pv = 0;
+           b_aux = 0, b_final = 0, b_pv = 0, b_args = 0, b_xring = 0;
     long long max_blocks = 0;
     bool fwd_only = false;   // objective NONE: forward sweep only, no trajectory or adjoint storage
 };
@@ -195,6 +195,7 @@ int plan(const lks_desc *d, Layout &L, std::string *err) {
     L.b_ckpt = (size_t)L.S * nf * L.F * e;
     L.b_traj = L.fwd_only ? 0 : (size_t)(L.K + 1) * D * L.F * e;
     L.b_box = L.fwd_only ? 0 : (size_t)L.K * nf * L.box.cells * e;
+    L.b_xring = 2 * nf * L.box.cells * e;  // kappa, u_S of the steps outside the stored segment
     L.b_kbar = L.fwd_only ? 0 : (size_t)L.box.cells * e;
     L.b_adj = L.fwd_only ? 0 : 2 * nf * L.F * e;
     L.b_final = nf * L.F * e;
@@ -207,8 +208,9 @@ int plan(const lks_desc *d, Layout &L, std::string *err) {
     if (d->kappa_static) L.b_aux += L.F * e;
     if (d->objective.kind != LKS_OBJ_NONE && d->objective.mask) L.b_aux += L.F;
     if (d->rho_init || d->u_init) L.b_aux += nf * L.F * e;
+    L.b_args = (size_t)N * (L.esz == 8 ? lks::args_bytes<double>() : lks::args_bytes<float>()) + 4096;
     L.bytes = L.b_state + L.b_ckpt + L.b_traj + L.b_box + L.b_kbar + L.b_adj + L.b_final +
-              L.b_design + L.b_aux + L.b_pv;
+              L.b_design + L.b_aux + L.b_pv + L.b_args + L.b_xring;
     if (d->hbm_budget_bytes && L.bytes > d->hbm_budget_bytes)
         return fail(err, LKS_ENOMEM, "context needs " + std::to_string(L.bytes) +
                                           " bytes, over the HBM budget");
@@ -231,7 +233,7 @@ struct lks_ctx {
     // device memory
     char *state = nullptr, *ckpt = nullptr, *traj = nullptr, *box = nullptr, *kbar = nullptr,
          *adj = nullptr, *fin = nullptr, *gamma = nullptr, *kref = nullptr, *sens = nullptr,
-         *kstatic = nullptr, *init = nullptr, *pv = nullptr;
+         *kstatic = nullptr, *init = nullptr, *pv = nullptr, *xring = nullptr;
     double *kprime = nullptr, *G = nullptr, *jn = nullptr, *partials = nullptr;
     unsigned int *counter = nullptr;
     int *flag = nullptr;
@@ -254,6 +256,11 @@ struct lks_ctx {
     } cs;
     double *jn_host = nullptr;  // pinned
     int *flag_host = nullptr;   // pinned
+    // per-step kernel argument blocks of one sweep: built on the host, uploaded once per sweep
+    char *argdev = nullptr;
+    char *arghost = nullptr;    // pinned
+    size_t argcap = 0;
+    long long *tile0 = nullptr; // device {0}: the single job of a one-job launch
     void *out_dev = nullptr;    // caller's device buffer for dJ/dgamma
     hipEvent_t done_ev = nullptr;
 
@@ -357,45 +364,140 @@ struct Timed {
     }
 };
 
+// kappa and u_S of one step on its footprint box: (1 + dim) arrays of box.cells values.  The
+// forward sweep keeps them in a two-slot ring (step n in slot n % 2) except in the last segment,
+// whose steps go to the box store (slot j - 1 for the j-th step of the segment) because the
+// reverse sweep reads them; a recomputed segment writes the box store the same way.
 template <typename T>
-lks::FwdArgs<T> make_fwd_args(lks_ctx *c, int n, const T *rin, const T *const uin[3], T *rout,
-                              T *const uout[3], int box_slot, bool objective) {
+T *box_slot(lks_ctx *c, bool ring, int slot) {
+    return reinterpret_cast<T *>(ring ? c->xring : c->box) + (long long)slot * (1 + c->d.dim) * c->L.box.cells;
+}
+
+template <typename T>
+T *fwd_loc(lks_ctx *c, int n) {
+    const int seg = (n - 1) / c->L.K;
+    if (seg == c->L.S - 1 && !c->L.fwd_only) return box_slot<T>(c, false, n - seg * c->L.K - 1);
+    return box_slot<T>(c, true, n & 1);
+}
+
+template <typename T>
+T *rec_loc(lks_ctx *c, int seg, int n) { return box_slot<T>(c, false, n - seg * c->L.K - 1); }
+
+template <typename T>
+lks::FwdArgs<T> base_fwd_args(lks_ctx *c) {
     lks::FwdArgs<T> a{};
     a.g = c->L.g;
     a.bc = bc_params<T>(c->d);
     a.A = (T)(4.5 * (1.0 / 6.0 - c->d.nu));
     for (int k = 0; k < 3; ++k) a.gf[k] = k < c->d.dim ? (T)c->d.body_force[k] : T(0);
+    a.kstatic = reinterpret_cast<const T *>(c->kstatic);
+    a.des = design<T>(c);
+    a.box = c->L.box;
+    return a;
+}
+
+template <typename T>
+void set_next(lks_ctx *c, lks::FwdArgs<T> &a, int n, T *knext) {
+    a.mode |= lks::FWD_TRANSFER_NEXT;
+    a.mnext = c->L.steps[n];
+    a.knext = knext;
+    for (int k = 0; k < 3; ++k) a.usnext[k] = k < c->d.dim ? knext + (1 + k) * c->L.box.cells : nullptr;
+}
+
+// forward step n: reads kappa, u_S of step n at kin; if knext is set, its extra blocks transfer
+// step n + 1 into knext
+template <typename T>
+lks::FwdArgs<T> make_fwd_args(lks_ctx *c, int n, const T *rin, const T *const uin[3], T *rout,
+                              T *const uout[3], const T *kin, T *knext, bool objective) {
+    lks::FwdArgs<T> a = base_fwd_args<T>(c);
     a.rin = rin;
     a.rout = rout;
     for (int k = 0; k < 3; ++k) {
         a.uin[k] = k < c->d.dim ? uin[k] : nullptr;
         a.uout[k] = k < c->d.dim ? uout[k] : nullptr;
     }
-    a.kstatic = reinterpret_cast<const T *>(c->kstatic);
-    a.des = design<T>(c);
     a.m = c->L.steps[n];
-    a.box = c->L.box;
-    if (box_slot >= 0) {
-        T *b = reinterpret_cast<T *>(c->box) + (long long)box_slot * (1 + c->d.dim) * c->L.box.cells;
-        a.kbox = b;
-        for (int k = 0; k < 3; ++k) a.usbox[k] = k < c->d.dim ? b + (1 + k) * c->L.box.cells : nullptr;
-    }
+    a.kin = kin;
+    for (int k = 0; k < 3; ++k) a.usin[k] = k < c->d.dim ? kin + (1 + k) * c->L.box.cells : nullptr;
+    a.mode = lks::FWD_STENCIL;
+    if (knext) set_next<T>(c, a, n + 1, knext);
     a.obj = obj_params(c, n);
     if (!objective) a.obj.active = 0;
     return a;
 }
 
+// transfer-only launch: kappa, u_S of step n into kdst (before the first step of a sweep)
 template <typename T>
-int launch_step_fwd(lks_ctx *c, int n, const T *rin, const T *const uin[3], T *rout,
-                    T *const uout[3], int box_slot, bool objective) {
-    const lks::FwdArgs<T> a = make_fwd_args<T>(c, n, rin, uin, rout, uout, box_slot, objective);
+lks::FwdArgs<T> make_xfer_args(lks_ctx *c, int n, T *kdst) {
+    lks::FwdArgs<T> a = base_fwd_args<T>(c);
+    a.m = c->L.steps[n];
+    set_next<T>(c, a, n, kdst);
+    return a;
+}
+
+// blocks of one forward launch: the stencil tiles, then the transfer blocks
+long long fwd_tiles(const lks_ctx *c, int mode) {
+    long long t = 0;
+    if (mode & lks::FWD_STENCIL)
+        t += c->d.dim == 2 ? lks::tiles2d_fwd(c->L.g) : lks::tiles3d(c->L.g, (int)c->L.esz);
+    if (mode & lks::FWD_TRANSFER_NEXT) t += lks::xfer_blocks(c->d.dim, c->L.box.cells, (int)c->L.esz);
+    return t;
+}
+
+// one-job launches: the argument block lives in device memory (see upload_args)
+template <typename T>
+hipError_t launch_fwd_raw(lks_ctx *c, const lks::FwdArgs<T> *dargs, long long ntiles) {
+    return c->d.dim == 2 ? lks::launch_fwd2d_batch<T>(dargs, c->tile0, 1, ntiles, c->stream)
+                         : lks::launch_fwd3d_batch<T>(dargs, c->tile0, 1, ntiles, c->d.lattice, c->stream);
+}
+
+// one forward step (timed as kind 0); mode is the host copy's mode
+template <typename T>
+int launch_fwd_dev(lks_ctx *c, const lks::FwdArgs<T> *dargs, int mode) {
     hipError_t e;
     {
         Timed t(c, 0);
-        e = c->d.dim == 2 ? lks::launch_fwd2d<T>(a, c->stream)
-                          : lks::launch_fwd3d<T>(a, c->d.lattice, c->stream);
+        e = launch_fwd_raw<T>(c, dargs, fwd_tiles(c, mode));
     }
     HIPCHK(c, e);
+    return LKS_OK;
+}
+
+// transfer-only launch (not part of the per-step timing)
+template <typename T>
+int launch_xfer_dev(lks_ctx *c, const lks::FwdArgs<T> *dargs) {
+    HIPCHK(c, (launch_fwd_raw<T>(c, dargs, fwd_tiles(c, lks::FWD_TRANSFER_NEXT))));
+    return LKS_OK;
+}
+
+template <typename T>
+int launch_adj_dev(lks_ctx *c, const lks::AdjArgs<T> *dargs, const lks::SensArgs<T> *dsens) {
+    hipError_t e;
+    {
+        Timed t(c, 1);
+        e = c->d.dim == 2
+                ? lks::launch_adj2d_batch<T>(dargs, c->tile0, 1, lks::tiles2d(c->L.g), c->stream)
+                : lks::launch_adj3d_batch<T>(dargs, c->tile0, (c->L.ncell + lks::kBlockHost - 1) / lks::kBlockHost,
+                                             c->tile0, lks::tiles3d(c->L.g, (int)c->L.esz), 1,
+                                             c->d.lattice, c->stream);
+    }
+    HIPCHK(c, e);
+    {
+        Timed t(c, 2);
+        e = lks::launch_sens_batch<T>(dsens, c->tile0, 1, (c->L.nd + lks::kBlockHost - 1) / lks::kBlockHost,
+                                      c->stream);
+    }
+    HIPCHK(c, e);
+    return LKS_OK;
+}
+
+// copy `bytes` of argument blocks (already written to the pinned staging area) to the device
+int upload_args(lks_ctx *c, size_t bytes) {
+    if (bytes > c->argcap) {
+        c->err = "argument staging area too small";
+        return LKS_EINVAL;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->argdev, c->arghost, bytes, hipMemcpyHostToDevice, c->stream));
     return LKS_OK;
 }
 
@@ -457,6 +559,33 @@ int forward_impl(lks_ctx *c, const void *gamma, double *J) {
         for (int k = 0; k < 3; ++k) ia.uout[k] = st[0].u[k];
         HIPCHK(c, lks::launch_init<T>(ia, c->stream));
     }
+    // argument blocks of every step of the sweep (the pointer pattern is fixed in advance)
+    {
+        auto *fa = reinterpret_cast<lks::FwdArgs<T> *>(c->arghost);
+        int cur = 0;
+        for (int n = 1; n <= N; ++n) {
+            const int seg = (n - 1) / K, j = n - seg * K;
+            const bool last = seg == S - 1 && !L.fwd_only;
+            T *uin[3], *uout[3];
+            if (last) {
+                traj_slot<T>(c, j - 1, uin);
+                traj_slot<T>(c, j, uout);
+            } else {
+                for (int k = 0; k < 3; ++k) {
+                    uin[k] = st[cur].u[k];
+                    uout[k] = st[1 - cur].u[k];
+                }
+            }
+            fa[n - 1] = make_fwd_args<T>(c, n, st[cur].r, uin, st[1 - cur].r, uout, fwd_loc<T>(c, n),
+                                         n < N ? fwd_loc<T>(c, n + 1) : nullptr, true);
+            cur = 1 - cur;
+        }
+        fa[N] = make_xfer_args<T>(c, 1, fwd_loc<T>(c, 1));
+        if ((rc = upload_args(c, (size_t)(N + 1) * sizeof(lks::FwdArgs<T>)))) return rc;
+    }
+    const auto *dfa = reinterpret_cast<const lks::FwdArgs<T> *>(c->argdev);
+    const auto *hfa = reinterpret_cast<const lks::FwdArgs<T> *>(c->arghost);
+    if ((rc = launch_xfer_dev<T>(c, dfa + N))) return rc;
     int cur = 0;
     for (int n = 1; n <= N; ++n) {
         const int seg = (n - 1) / K, j = n - seg * K;
@@ -473,18 +602,7 @@ int forward_impl(lks_ctx *c, const void *gamma, double *J) {
                 if ((rc = copy_fields<T>(c, t0[0], st[cur].u[0], D))) return rc;
             }
         }
-        T *uin[3], *uout[3];
-        if (last) {
-            traj_slot<T>(c, j - 1, uin);
-            traj_slot<T>(c, j, uout);
-        } else {
-            for (int k = 0; k < 3; ++k) {
-                uin[k] = st[cur].u[k];
-                uout[k] = st[1 - cur].u[k];
-            }
-        }
-        if ((rc = launch_step_fwd<T>(c, n, st[cur].r, uin, st[1 - cur].r, uout, last ? j - 1 : -1, true)))
-            return rc;
+        if ((rc = launch_fwd_dev<T>(c, dfa + (n - 1), hfa[n - 1].mode))) return rc;
         cur = 1 - cur;
     }
     if (c->d.objective.kind != LKS_OBJ_NONE)  // j^n of every step of the window, in block order
@@ -576,10 +694,45 @@ int adjoint_impl(lks_ctx *c) {
     const int D = c->d.dim, N = c->d.nsteps, K = L.K, S = L.S;
     int rc;
     Fields<T> st[2] = {state_fields<T>(c, c->state), state_fields<T>(c, c->field(c->state, 1 + D))};
-    Fields<T> ad[2] = {state_fields<T>(c, c->adj), state_fields<T>(c, c->field(c->adj, 1 + D))};
-    HIPCHK(c, lks::launch_fill<T>(ad[0].r, T(0), (long long)(1 + D) * L.F, c->stream));
+    Fields<T> ad = state_fields<T>(c, c->adj);
+    // argument blocks: recomputed steps (every segment but the last), adjoint steps, gathers
+    // layout: recomputed steps [0, nrec), one transfer-only block per recomputed segment, then
+    // the adjoint steps and the gathers
+    const int nrec = (S - 1) * K, nfa = nrec + (S - 1);
+    auto *ra = reinterpret_cast<lks::FwdArgs<T> *>(c->arghost);
+    auto *aa = reinterpret_cast<lks::AdjArgs<T> *>(c->arghost + (size_t)nfa * sizeof(lks::FwdArgs<T>));
+    auto *sa = reinterpret_cast<lks::SensArgs<T> *>(reinterpret_cast<char *>(aa) + (size_t)N * sizeof(lks::AdjArgs<T>));
+    const size_t bytes = (size_t)nfa * sizeof(lks::FwdArgs<T>) + (size_t)N * (sizeof(lks::AdjArgs<T>) + sizeof(lks::SensArgs<T>));
+    {
+        int acur = 0;
+        for (int seg = S - 1; seg >= 0; --seg) {
+            const int n0 = seg * K + 1, n1 = std::min((seg + 1) * K, N);
+            if (seg != S - 1) {
+                int cur = 0;
+                for (int n = n0; n <= n1; ++n) {
+                    const int j = n - seg * K;
+                    T *uin[3], *uout[3];
+                    traj_slot<T>(c, j - 1, uin);
+                    traj_slot<T>(c, j, uout);
+                    ra[n - 1] = make_fwd_args<T>(c, n, st[cur].r, uin, st[1 - cur].r, uout, rec_loc<T>(c, seg, n),
+                                                 n < n1 ? rec_loc<T>(c, seg, n + 1) : nullptr, false);
+                    cur = 1 - cur;
+                }
+                ra[nrec + seg] = make_xfer_args<T>(c, n0, rec_loc<T>(c, seg, n0));
+            }
+            for (int n = n1; n >= n0; --n) {
+                aa[n - 1] = make_adj_args<T>(c, n, n - seg * K, acur);
+                sa[n - 1] = make_sens_args<T>(c, n);
+                acur = 1 - acur;
+            }
+        }
+        if ((rc = upload_args(c, bytes))) return rc;
+    }
+    const auto *dra = reinterpret_cast<const lks::FwdArgs<T> *>(c->argdev);
+    const auto *daa = reinterpret_cast<const lks::AdjArgs<T> *>(c->argdev + (size_t)nfa * sizeof(lks::FwdArgs<T>));
+    const auto *dsa = reinterpret_cast<const lks::SensArgs<T> *>(reinterpret_cast<const char *>(daa) + (size_t)N * sizeof(lks::AdjArgs<T>));
+    HIPCHK(c, lks::launch_fill<T>(ad.r, T(0), (long long)(1 + D) * L.F, c->stream));
     HIPCHK(c, lks::launch_fill<double>(c->G, 0.0, L.nd, c->stream));
-    int acur = 0;
     for (int seg = S - 1; seg >= 0; --seg) {
         const int n0 = seg * K + 1, n1 = std::min((seg + 1) * K, N);
         if (seg != S - 1) {  // restore the checkpoint and recompute the segment
@@ -588,34 +741,12 @@ int adjoint_impl(lks_ctx *c) {
             traj_slot<T>(c, 0, t0);
             if ((rc = copy_fields<T>(c, st[0].r, ck, 1))) return rc;
             if ((rc = copy_fields<T>(c, t0[0], ck + L.F, D))) return rc;
-            int cur = 0;
-            for (int n = n0; n <= n1; ++n) {
-                const int j = n - seg * K;
-                T *uin[3], *uout[3];
-                traj_slot<T>(c, j - 1, uin);
-                traj_slot<T>(c, j, uout);
-                if ((rc = launch_step_fwd<T>(c, n, st[cur].r, uin, st[1 - cur].r, uout, j - 1, false)))
-                    return rc;
-                cur = 1 - cur;
-            }
+            if ((rc = launch_xfer_dev<T>(c, dra + nrec + seg))) return rc;
+            for (int n = n0; n <= n1; ++n)
+                if ((rc = launch_fwd_dev<T>(c, dra + (n - 1), ra[n - 1].mode))) return rc;
         }
-        for (int n = n1; n >= n0; --n) {
-            const int j = n - seg * K;
-            const lks::AdjArgs<T> a = make_adj_args<T>(c, n, j, acur);
-            hipError_t e;
-            {
-                Timed t(c, 1);
-                e = D == 2 ? lks::launch_adj2d<T>(a, c->stream) : lks::launch_adj3d<T>(a, c->d.lattice, c->stream);
-            }
-            HIPCHK(c, e);
-            const lks::SensArgs<T> sa = make_sens_args<T>(c, n);
-            {
-                Timed t(c, 2);
-                e = lks::launch_sens<T>(sa, c->stream);
-            }
-            HIPCHK(c, e);
-            acur = 1 - acur;
-        }
+        for (int n = n1; n >= n0; --n)
+            if ((rc = launch_adj_dev<T>(c, daa + (n - 1), dsa + (n - 1)))) return rc;
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if ((rc = flush_timing(c))) return rc;
@@ -655,10 +786,19 @@ int create_impl(const lks_desc *d, lks_ctx *c) {
     ALLOC(ckpt, L.b_ckpt)
     ALLOC(traj, L.b_traj)
     ALLOC(box, L.b_box)
+    ALLOC(xring, L.b_xring)
     ALLOC(kbar, L.b_kbar)
     ALLOC(adj, L.b_adj)
     ALLOC(fin, L.b_final)
     ALLOC(pv, L.b_pv)
+    ALLOC(argdev, L.b_args)
+    c->argcap = L.b_args - 256;  // the last 256 bytes hold tile0
+    if (hipHostMalloc(reinterpret_cast<void **>(&c->arghost), L.b_args, 0) != hipSuccess) {
+        c->arghost = nullptr;
+        c->err = "pinned host allocation failed";
+        return LKS_ENOMEM;
+    }
+    c->tile0 = reinterpret_cast<long long *>(c->argdev + L.b_args - 256);
     ALLOC(gamma, L.nd * e)
     ALLOC(kref, L.nd * e)
     ALLOC(sens, L.nd * e)
@@ -670,6 +810,7 @@ int create_impl(const lks_desc *d, lks_ctx *c) {
     ALLOC(counter, 64)
     c->flag = reinterpret_cast<int *>(reinterpret_cast<char *>(c->counter) + 32);
     HIPCHK(c, hipMemset(c->counter, 0, 64));
+    HIPCHK(c, hipMemset(c->tile0, 0, 256));
     // padded row tails are never written by the kernels: start every field buffer at zero
     for (char *b : {c->state, c->ckpt, c->traj, c->adj, c->fin})
         if (b) HIPCHK(c, hipMemset(b, 0, b == c->state ? L.b_state : b == c->ckpt ? L.b_ckpt
@@ -740,6 +881,8 @@ enum { PH_IDLE = 0, PH_FWD = 1, PH_ADJ_BEGIN = 2, PH_ADJ = 3, PH_REC_BEGIN = 4, 
 
 template <typename T>
 struct RoundLists {
+    std::vector<lks::FwdArgs<T>> pre[3];   // transfer-only launches, before the forward launches
+    std::vector<long long> ptiles[3];
     std::vector<lks::FwdArgs<T>> fwd[3];   // 2D, 3D D3Q19, 3D D3Q15
     std::vector<long long> ftiles[3];
     std::vector<lks::AdjArgs<T>> adj[3];
@@ -750,8 +893,9 @@ struct RoundLists {
 
 int list_of(const lks_ctx *c) { return c->d.dim == 2 ? 0 : (c->d.lattice == LKS_D3Q19 ? 1 : 2); }
 
-long long tiles_of(const lks_ctx *c) {
-    return c->d.dim == 2 ? lks::tiles2d(c->L.g) : lks::tiles3d(c->L.g, (int)c->L.esz);
+long long adj_tiles(const lks_ctx *c) {
+    if (c->d.dim == 2) return lks::tiles2d(c->L.g);
+    return lks::tiles3d(c->L.g, (int)c->L.esz);
 }
 
 template <typename T>
@@ -821,9 +965,13 @@ int plan_step(lks_ctx *c, RoundLists<T> &R, int *rc) {
                 uout[k] = st[1 - cs.cur].u[k];
             }
         }
-        R.fwd[li].push_back(make_fwd_args<T>(c, n, st[cs.cur].r, uin, st[1 - cs.cur].r, uout,
-                                             last ? j - 1 : -1, true));
-        R.ftiles[li].push_back(tiles_of(c));
+        if (n == 1) {
+            R.pre[li].push_back(make_xfer_args<T>(c, 1, fwd_loc<T>(c, 1)));
+            R.ptiles[li].push_back(fwd_tiles(c, lks::FWD_TRANSFER_NEXT));
+        }
+        R.fwd[li].push_back(make_fwd_args<T>(c, n, st[cs.cur].r, uin, st[1 - cs.cur].r, uout, fwd_loc<T>(c, n),
+                                             n < N ? fwd_loc<T>(c, n + 1) : nullptr, true));
+        R.ftiles[li].push_back(fwd_tiles(c, R.fwd[li].back().mode));
         cs.cur = 1 - cs.cur;
         cs.n = n + 1;
         return cs.n > N ? 1 : 0;
@@ -843,6 +991,8 @@ int plan_step(lks_ctx *c, RoundLists<T> &R, int *rc) {
         traj_slot<T>(c, 0, t0);
         if ((*rc = copy_fields<T>(c, st[0].r, ck, 1))) return 0;
         if ((*rc = copy_fields<T>(c, t0[0], ck + L.F, D))) return 0;
+        R.pre[li].push_back(make_xfer_args<T>(c, seg_lo(cs.seg), rec_loc<T>(c, cs.seg, seg_lo(cs.seg))));
+        R.ptiles[li].push_back(fwd_tiles(c, lks::FWD_TRANSFER_NEXT));
         cs.cur = 0;
         cs.n = seg_lo(cs.seg);
         cs.phase = PH_REC;
@@ -852,8 +1002,11 @@ int plan_step(lks_ctx *c, RoundLists<T> &R, int *rc) {
         T *uin[3], *uout[3];
         traj_slot<T>(c, j - 1, uin);
         traj_slot<T>(c, j, uout);
-        R.fwd[li].push_back(make_fwd_args<T>(c, n, st[cs.cur].r, uin, st[1 - cs.cur].r, uout, j - 1, false));
-        R.ftiles[li].push_back(tiles_of(c));
+        (void)j;
+        R.fwd[li].push_back(make_fwd_args<T>(c, n, st[cs.cur].r, uin, st[1 - cs.cur].r, uout,
+                                             rec_loc<T>(c, cs.seg, n),
+                                             n < seg_hi(cs.seg) ? rec_loc<T>(c, cs.seg, n + 1) : nullptr, false));
+        R.ftiles[li].push_back(fwd_tiles(c, R.fwd[li].back().mode));
         cs.cur = 1 - cs.cur;
         cs.n = n + 1;
         if (cs.n > seg_hi(cs.seg)) {
@@ -865,7 +1018,7 @@ int plan_step(lks_ctx *c, RoundLists<T> &R, int *rc) {
     if (cs.phase == PH_ADJ) {
         const int n = cs.n, j = n - cs.seg * K;
         R.adj[li].push_back(make_adj_args<T>(c, n, j, cs.acur));
-        R.atiles[li].push_back(tiles_of(c));
+        R.atiles[li].push_back(adj_tiles(c));
         R.ablk[li].push_back((L.ncell + lks::kBlockHost - 1) / lks::kBlockHost);
         R.sens.push_back(make_sens_args<T>(c, n));
         R.sblk.push_back((L.nd + lks::kBlockHost - 1) / lks::kBlockHost);
@@ -955,6 +1108,15 @@ int round_impl(lks_batch *b, lks_ctx *const *cs, int n, int *done) {
         int njobs;
     };
     std::vector<Launch> ls;
+    for (int li = 0; li < 3; ++li) {
+        if (!R.pre[li].empty()) {
+            std::vector<long long> p;
+            const long long tot = prefix(R.ptiles[li], p);
+            Launch L{0, li, put(R.pre[li].data(), R.pre[li].size() * sizeof(lks::FwdArgs<T>)),
+                     put(p.data(), p.size() * 8), 0, tot, 0, (int)R.pre[li].size()};
+            ls.push_back(L);
+        }
+    }
     for (int li = 0; li < 3; ++li) {
         if (!R.fwd[li].empty()) {
             std::vector<long long> p;
@@ -1102,6 +1264,7 @@ void lks_destroy(lks_ctx *c) {
     }
     if (c->done_ev) (void)hipEventDestroy(c->done_ev);
     if (c->jn_host) (void)hipHostFree(c->jn_host);
+    if (c->arghost) (void)hipHostFree(c->arghost);
     if (c->flag_host) (void)hipHostFree(c->flag_host);
     delete c;
 }

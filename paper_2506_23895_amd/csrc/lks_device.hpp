@@ -25,15 +25,16 @@ __device__ __forceinline__ bool on_face(const Geom &g, int a, int c) {
     return !g.per[a] && (c == 0 || c == g.n[a] - 1);
 }
 
-__device__ __forceinline__ float cospi_t(float v) { return cospif(v); }
-__device__ __forceinline__ double cospi_t(double v) { return cospi(v); }
+// cos(pi v / 2) for |v| < 2: the hardware cosine in single precision, cospi in double
+__device__ __forceinline__ float cos_half_pi(float v) { return __cosf(v * 1.57079632679489662f); }
+__device__ __forceinline__ double cos_half_pi(double v) { return cospi(v * 0.5); }
 
 // Transfer weight w(r) (Sec. 2.3 weight functions): LIN hat, or Peskin's cosine (1 + cos) / 4.
 template <typename T>
 __device__ __forceinline__ T wk(int weight, T d) {
     T a = fabs(d);
     if (weight == 1) return a < T(1) ? T(1) - a : T(0);
-    return a < T(2) ? T(0.25) * (T(1) + cospi_t(d * T(0.5))) : T(0);
+    return a < T(2) ? T(0.25) * (T(1) + cos_half_pi(d)) : T(0);
 }
 
 // kappa(x) = sum_xi W(x - x_ref(xi)) kappa_ref(xi) and u_S(x) = sum_xi W u_ref(xi) at one analysis
@@ -42,8 +43,8 @@ __device__ __forceinline__ T wk(int weight, T d) {
 // kernel support of x are scanned.  x - x_ref(xi) = R (p - xi); u_ref is affine in xi, so
 // sum W u_ref = Omega x ((x - xG) sum W - sum W (x - x_ref)) + uG sum W.
 template <typename T, int DIM>
-__device__ void gather_kappa(const Design<T> &des, const StepMotion &m, int x, int y, int z,
-                             T &kap, T us[3]) {
+__device__ __forceinline__ void gather_kappa(const Design<T> &des, const StepMotion &m, int x, int y,
+                                             int z, T &kap, T us[3]) {
     constexpr int dim = DIM;
     const double dx = x - m.xG[0], dy = y - m.xG[1], dz = (dim == 3) ? z - m.xG[2] : 0.0;
     double p[3];
@@ -69,25 +70,53 @@ __device__ void gather_kappa(const Design<T> &des, const StepMotion &m, int x, i
     T d0[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) d0[a] = R[3 * a] * f[0] + R[3 * a + 1] * f[1] + R[3 * a + 2] * f[2];
+    // along a candidate row (fixed j, k) d_a is affine in fi: d_a = c_a - fi R[3a]; the nodes
+    // with |d_a| < s on every axis form one interval of fi, so only that interval is scanned
+    // (slightly widened against rounding: nodes outside the support still get W = 0 below)
+    const T sT = (T)s, span = (T)(hi[0] - lo[0]);
+    T inv[3];
+#pragma unroll
+    for (int a = 0; a < dim; ++a) inv[a] = fabs(R[3 * a]) > T(1e-6) ? T(1) / R[3 * a] : T(0);
     T sW = 0, sWk = 0, sWd[3] = {0, 0, 0};
     for (int k = lo[2]; k <= hi[2]; ++k) {
         const T fk = (T)(k - lo[2]);
         for (int j = lo[1]; j <= hi[1]; ++j) {
             const T fj = (T)(j - lo[1]);
-            const T* krow = des.kref + (long long)des.nd[0] * (j + (long long)des.nd[1] * k);
-            for (int i = lo[0]; i <= hi[0]; ++i) {
-                const T fi = (T)(i - lo[0]);
-                T d[3] = {T(0), T(0), T(0)}, W = T(1);
+            T flo = T(0), fhi = span;
 #pragma unroll
-                for (int a = 0; a < dim; ++a) {
-                    d[a] = d0[a] - fi * R[3 * a] - fj * R[3 * a + 1] - fk * R[3 * a + 2];
-                    W *= wk<T>(des.weight, d[a]);
+            for (int a = 0; a < dim; ++a) {
+                const T ca = d0[a] - fj * R[3 * a + 1] - fk * R[3 * a + 2];
+                if (inv[a] != T(0)) {
+                    const T t1 = (ca - sT) * inv[a], t2 = (ca + sT) * inv[a];
+                    flo = fmax(flo, fmin(t1, t2) - T(1e-3));
+                    fhi = fmin(fhi, fmax(t1, t2) + T(1e-3));
+                } else if (fabs(ca) >= sT + T(1e-3)) {
+                    fhi = T(-1);
                 }
-                if (W == T(0)) continue;
-                sW += W;
-                sWk += W * krow[i];
+            }
+            if (flo > fhi) continue;
+            const int i0 = lo[0] + (int)ceil(flo), i1 = lo[0] + (int)floor(fhi);
+            const T *krow = des.kref + (long long)des.nd[0] * (j + (long long)des.nd[1] * k);
+            for (int i = i0; i <= i1; i += 4) {  // four candidates' loads in flight together
+                T kv[4];
 #pragma unroll
-                for (int a = 0; a < dim; ++a) sWd[a] += W * d[a];
+                for (int u = 0; u < 4; ++u) kv[u] = i + u <= i1 ? krow[i + u] : T(0);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (i + u > i1) break;
+                    const T fi = (T)(i + u - lo[0]);
+                    T d[3] = {T(0), T(0), T(0)}, W = T(1);
+#pragma unroll
+                    for (int a = 0; a < dim; ++a) {
+                        d[a] = d0[a] - fi * R[3 * a] - fj * R[3 * a + 1] - fk * R[3 * a + 2];
+                        W *= wk<T>(des.weight, d[a]);
+                    }
+                    if (W == T(0)) continue;
+                    sW += W;
+                    sWk += W * kv[u];
+#pragma unroll
+                    for (int a = 0; a < dim; ++a) sWd[a] += W * d[a];
+                }
             }
         }
     }
@@ -110,6 +139,26 @@ __device__ __forceinline__ long long box_index(const BoxGeom &b, const StepMotio
                                                int x, int y, int z) {
     return (x - m.lo[0]) + (long long)(y - m.lo[1]) * b.bsy +
            (dim == 3 ? (long long)(z - m.lo[2]) * b.bsz : 0LL);
+}
+
+// Transfer of one step onto its footprint box, one thread per box cell: writes kappa and u_S
+// into box arrays (fixed extent bn, this step's origin m.lo).  Launched as extra blocks of the
+// previous step's stencil launch, so it runs off the stencil's critical path.
+template <typename T, int DIM, int NT>
+__device__ __forceinline__ void transfer_box(const Design<T> &des, const StepMotion &m,
+                                             const BoxGeom &box, T *kout, T *const usout[3],
+                                             long long blk) {
+    const long long cell = blk * NT + threadIdx.x;
+    const int ex = m.hi[0] - m.lo[0] + 1, ey = m.hi[1] - m.lo[1] + 1;
+    const int ez = DIM == 3 ? m.hi[2] - m.lo[2] + 1 : 1;
+    if (cell >= (long long)ex * ey * ez) return;
+    const int bx = (int)(cell % ex), by = (int)((cell / ex) % ey), bz = (int)(cell / ((long long)ex * ey));
+    T kap, us[3];
+    gather_kappa<T, DIM>(des, m, m.lo[0] + bx, m.lo[1] + by, DIM == 3 ? m.lo[2] + bz : 0, kap, us);
+    const long long bi = bx + by * box.bsy + (DIM == 3 ? bz * box.bsz : 0LL);
+    kout[bi] = kap;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) usout[a][bi] = us[a];
 }
 
 // ---- composite boundary rules ------------------------------------------------------------

@@ -71,11 +71,16 @@ struct FwdArgs {
     const T *kstatic;
     Design<T> des;
     StepMotion m;
-    T *kbox;        // optional: kappa and u_S written on the footprint box
-    T *usbox[3];
     BoxGeom box;
+    const T *kin;       // kappa and u_S of this step on its footprint box
+    const T *usin[3];
+    int mode;           // bit 0: run the stencil; bit 1: transfer the next step
+    StepMotion mnext;   // motion of the step transferred by the extra blocks
+    T *knext;           // where the extra blocks write the next step's kappa and u_S
+    T *usnext[3];
     ObjParams obj;
 };
+enum { FWD_STENCIL = 1, FWD_TRANSFER_NEXT = 2 };
 
 template <typename T>
 struct AdjArgs {
@@ -121,12 +126,14 @@ struct InitArgs {
     T *uout[3];
 };
 
+// bytes of argument blocks one time step of one context needs (forward + recompute + adjoint
+// + gather)
+template <typename T>
+constexpr size_t args_bytes() {
+    return 2 * sizeof(FwdArgs<T>) + sizeof(AdjArgs<T>) + sizeof(SensArgs<T>);
+}
+
 // ---- launchers (defined in the .hip files) -----------------------------------------------
-template <typename T> hipError_t launch_fwd2d(const FwdArgs<T> &a, hipStream_t s);
-template <typename T> hipError_t launch_adj2d(const AdjArgs<T> &a, hipStream_t s);
-template <typename T> hipError_t launch_fwd3d(const FwdArgs<T> &a, int lattice, hipStream_t s);
-template <typename T> hipError_t launch_adj3d(const AdjArgs<T> &a, int lattice, hipStream_t s);
-template <typename T> hipError_t launch_sens(const SensArgs<T> &a, hipStream_t s);
 template <typename T> hipError_t launch_init(const InitArgs<T> &a, hipStream_t s);
 template <typename T>
 hipError_t launch_design_prep(const T *gamma, T *kref, double *kprime, long long nd, int interp,
@@ -159,8 +166,12 @@ hipError_t launch_adj3d_batch(const AdjArgs<T> *args, const long long *blk0, lon
 template <typename T>
 hipError_t launch_sens_batch(const SensArgs<T> *args, const long long *blk0, int njobs, long long nblk,
                              hipStream_t s);
-long long tiles2d(const Geom &g);
+long long tiles2d(const Geom &g);      // adjoint tiles
+long long tiles2d_fwd(const Geom &g);  // forward blocks (four wave strips each)
 long long tiles3d(const Geom &g, int esz);
+// blocks a forward launch appends to transfer the next step onto a box of `cells` cells
+long long xfer_blocks(int dim, long long cells, int esz);
+long long xfer_blocks3d(long long cells, int esz);
 
 // grid sizes of the stencil launches (used by the host to size the partials buffer)
 long long fwd_blocks(const Geom &g, int lattice, int esz);

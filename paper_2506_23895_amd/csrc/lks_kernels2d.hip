@@ -31,143 +31,226 @@ __device__ constexpr double wt(int i) { return i == 0 ? W0 : (i < 5 ? WA : WD); 
 
 constexpr int TX = 64, TY = 8;
 
-template <typename T>
-__device__ __forceinline__ void fwd2d_body(const FwdArgs<T> &a, int bx, int by, long long blin) {
-    constexpr int UX = TX + 4, UY = TY + 4;  // u staged with halo 2, origin (x0-2, y0-2)
-    constexpr int EX = TX + 2, EY = TY + 2;  // rho and E_i with halo 1, origin (x0-1, y0-1)
-    __shared__ T su[2][UY][UX];
-    __shared__ T sr[EY][EX];
-    __shared__ T sE[8][EY][EX];
-    __shared__ double sh4[4];
+// ---- lane shifts within a 64-wide wavefront (DPP wave_shr:1 / wave_shl:1; edge lanes read 0) ----
+__device__ __forceinline__ int dpp_l(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, true); }
+__device__ __forceinline__ int dpp_r(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, true); }
+// value of lane i-1 / lane i+1
+__device__ __forceinline__ float from_left(float v) { return __builtin_bit_cast(float, dpp_l(__builtin_bit_cast(int, v))); }
+__device__ __forceinline__ float from_right(float v) { return __builtin_bit_cast(float, dpp_r(__builtin_bit_cast(int, v))); }
+__device__ __forceinline__ double from_left(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = dpp_l((int)(b & 0xffffffffLL)), hi = dpp_l((int)(b >> 32));
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double from_right(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = dpp_r((int)(b & 0xffffffffLL)), hi = dpp_r((int)(b >> 32));
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
 
-    const int tid = threadIdx.x;
-    const int x0 = bx * TX, y0 = by * TY;
+// Forward step as wave strips marching along y.  Lane l of wave w holds column
+// c = 60 * strip - 2 + l; lanes 2..61 produce outputs, lanes 0, 1, 62, 63 are the column halo.
+// A wave owns RY output rows: it issues the loads of every velocity row it needs (RY + 5) and
+// every density row (RY + 2) into registers up front, then walks the rows as they arrive.  Per
+// row r the lane evaluates the strain and the nine E_i of its own node once, adds the ones pulled
+// by its own column (c_x = 0) into three in-flight output rows, and sums per target row the ones
+// pulled by column c+1 (c_x = +1) and by column c-1 (c_x = -1); those sums reach the neighbouring
+// lanes through one lane shift each when their target row completes.
+#ifndef LKS_FWD2D_RY
+#define LKS_FWD2D_RY 4
+#endif
+constexpr int SW = 60;            // output columns per wave strip
+constexpr int RY = LKS_FWD2D_RY;  // output rows per wave
+constexpr int WPB = kBlock / 64;
+
+// face nodes written from interior node (c, o), with their objective contribution
+template <typename T>
+__device__ __noinline__ double fwd2d_push(const FwdArgs<T> &a, int c, int o, T rs, T nux, T nuy,
+                                          bool obj_on) {
+    const Geom &g = a.g;
+    double j = 0.0;
+    const int c3[3] = {c, o, 0};
+    const T v[4] = {rs, nux, nuy, T(0)};
+    push_boundary<T, 2>(g, a.bc, c3, v, [&](const int p[3], const T pv[4]) {
+        const long long pi = p[0] + p[1] * g.sy;
+        a.rout[pi] = pv[0];
+        a.uout[0][pi] = pv[1];
+        a.uout[1][pi] = pv[2];
+        if (obj_on && !obj_uses_kappa(a.obj.kind) && (!a.obj.mask || a.obj.mask[pi])) {
+            const T pu[3] = {pv[1], pv[2], T(0)}, z3[3] = {0, 0, 0};
+            j += obj_density<T>(a.obj, p[0], p[1], 0, (double)pv[0], pu, T(0), z3);
+        }
+    });
+    return j;
+}
+
+template <typename T>
+__device__ __forceinline__ void fwd2d_body(const FwdArgs<T> &a, int bx, int by, long long slot0) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const Geom &g = a.g;
     const int nx = g.n[0], ny = g.n[1];
-
-    for (int i = tid; i < UX * UY; i += kBlock) {
-        const int lx = i % UX, ly = i / UX;
-        int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
-        T ux = 0, uy = 0;
-        if (wrapc(gx, nx, g.per[0]) && wrapc(gy, ny, g.per[1])) {
-            const long long idx = gx + gy * g.sy;
-            ux = a.uin[0][idx];
-            uy = a.uin[1][idx];
-        }
-        su[0][ly][lx] = ux;
-        su[1][ly][lx] = uy;
-    }
-    for (int i = tid; i < EX * EY; i += kBlock) {
-        const int lx = i % EX, ly = i / EX;
-        int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
-        T r = 0;
-        if (wrapc(gx, nx, g.per[0]) && wrapc(gy, ny, g.per[1])) r = a.rin[gx + gy * g.sy];
-        sr[ly][lx] = r;
-    }
-    __syncthreads();
-
-    // equilibrium of every staged node (Sec. 2.2): E_i = w_i [rho + 3 c.u + 4.5 (c.u)^2 - 1.5 u^2
-    // + A c.S.c], S_ab = d_b u_a + d_a u_b; the rest direction is evaluated at the puller
-    const T A = a.A;
-    for (int i = tid; i < EX * EY; i += kBlock) {
-        const int lx = i % EX, ly = i / EX;
-        int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
-        if (!g.per[0] && (gx < 0 || gx >= nx)) continue;
-        if (!g.per[1] && (gy < 0 || gy >= ny)) continue;
-        const int ux_ = lx + 1, uy_ = ly + 1;  // position in su
-        const int cxn = gx, cyn = gy;          // true coordinate on non-periodic axes
-        T dxux, dxuy, dyux, dyuy;
-        if (!g.per[0] && (cxn == 0 || cxn == nx - 1)) {
-            const int s = cxn == 0 ? 1 : -1;
-            dxux = T(s) * (T(-1.5) * su[0][uy_][ux_] + T(2) * su[0][uy_][ux_ + s] - T(0.5) * su[0][uy_][ux_ + 2 * s]);
-            dxuy = T(s) * (T(-1.5) * su[1][uy_][ux_] + T(2) * su[1][uy_][ux_ + s] - T(0.5) * su[1][uy_][ux_ + 2 * s]);
-        } else {
-            dxux = T(0.5) * (su[0][uy_][ux_ + 1] - su[0][uy_][ux_ - 1]);
-            dxuy = T(0.5) * (su[1][uy_][ux_ + 1] - su[1][uy_][ux_ - 1]);
-        }
-        if (!g.per[1] && (cyn == 0 || cyn == ny - 1)) {
-            const int s = cyn == 0 ? 1 : -1;
-            dyux = T(s) * (T(-1.5) * su[0][uy_][ux_] + T(2) * su[0][uy_ + s][ux_] - T(0.5) * su[0][uy_ + 2 * s][ux_]);
-            dyuy = T(s) * (T(-1.5) * su[1][uy_][ux_] + T(2) * su[1][uy_ + s][ux_] - T(0.5) * su[1][uy_ + 2 * s][ux_]);
-        } else {
-            dyux = T(0.5) * (su[0][uy_ + 1][ux_] - su[0][uy_ - 1][ux_]);
-            dyuy = T(0.5) * (su[1][uy_ + 1][ux_] - su[1][uy_ - 1][ux_]);
-        }
-        const T ux = su[0][uy_][ux_], uy = su[1][uy_][ux_], r = sr[ly][lx];
-        const T a0 = r - T(1.5) * (ux * ux + uy * uy);
-        const T bx = T(3) * ux, by = T(3) * uy;
-        const T txx = T(4.5) * ux * ux + A * T(2) * dxux;
-        const T tyy = T(4.5) * uy * uy + A * T(2) * dyuy;
-        const T txy2 = T(2) * (T(4.5) * ux * uy + A * (dyux + dxuy));
-        const T wa = T(d2q9::WA), wd = T(d2q9::WD);
-        sE[0][ly][lx] = wa * (a0 + bx + txx);                    // ( 1, 0)
-        sE[1][ly][lx] = wa * (a0 + by + tyy);                    // ( 0, 1)
-        sE[2][ly][lx] = wa * (a0 - bx + txx);                    // (-1, 0)
-        sE[3][ly][lx] = wa * (a0 - by + tyy);                    // ( 0,-1)
-        sE[4][ly][lx] = wd * (a0 + bx + by + txx + tyy + txy2);  // ( 1, 1)
-        sE[5][ly][lx] = wd * (a0 - bx + by + txx + tyy - txy2);  // (-1, 1)
-        sE[6][ly][lx] = wd * (a0 - bx - by + txx + tyy + txy2);  // (-1,-1)
-        sE[7][ly][lx] = wd * (a0 + bx - by + txx + tyy - txy2);  // ( 1,-1)
-    }
-    __syncthreads();
-
-    double jacc = 0.0;
+    const int strip = bx * WPB + w;
+    const long long pslot = slot0 + w;
     const bool obj_on = a.obj.active && a.obj.kind != OBJ_NONE;
-    for (int k = 0; k < (TX * TY) / kBlock; ++k) {
-        const int lx = tid % TX, ly = tid / TX + k * (kBlock / TX);
-        const int gx = x0 + lx, gy = y0 + ly;
-        if (gx >= nx || gy >= ny) continue;
-        if (on_face(g, 0, gx) || on_face(g, 1, gy)) continue;  // written by push_boundary
-        const int ex = lx + 1, ey = ly + 1;
-        const T ux = su[0][ly + 2][lx + 2], uy = su[1][ly + 2][lx + 2], r = sr[ey][ex];
-        const T e0 = T(d2q9::W0) * (r - T(1.5) * (ux * ux + uy * uy));
-        // pull from x - c_i
-        const T e1 = sE[0][ey][ex - 1], e2 = sE[1][ey - 1][ex], e3 = sE[2][ey][ex + 1],
-                e4 = sE[3][ey + 1][ex], e5 = sE[4][ey - 1][ex - 1], e6 = sE[5][ey - 1][ex + 1],
-                e7 = sE[6][ey + 1][ex + 1], e8 = sE[7][ey + 1][ex - 1];
-        const T rs = e0 + (e1 + e2 + e3 + e4) + (e5 + e6 + e7 + e8);
-        const T mx = (e1 - e3) + (e5 - e6) + (e8 - e7);
-        const T my = (e2 - e4) + (e5 + e6) - (e7 + e8);
-        T kap = 0, us[3] = {0, 0, 0};
-        const bool inb = in_box(a.m, 2, gx, gy, 0);
-        if (inb) gather_kappa<T, 2>(a.des, a.m, gx, gy, 0, kap, us);
-        const long long idx = gx + gy * g.sy;
-        const T ks = a.kstatic ? a.kstatic[idx] : T(0);
-        const T inv = T(1) / (T(1) + kap + ks);
-        const T nux = (mx + kap * us[0] + a.gf[0]) * inv;
-        const T nuy = (my + kap * us[1] + a.gf[1]) * inv;
-        a.rout[idx] = rs;
-        a.uout[0][idx] = nux;
-        a.uout[1][idx] = nuy;
-        if (a.kbox && inb) {
-            const long long bi = box_index(a.box, a.m, 2, gx, gy, 0);
-            a.kbox[bi] = kap;
-            a.usbox[0][bi] = us[0];
-            a.usbox[1][bi] = us[1];
-        }
-        const T uv[3] = {nux, nuy, T(0)};
-        if (obj_on && (!a.obj.mask || a.obj.mask[idx]))
-            jacc += obj_density<T>(a.obj, gx, gy, 0, (double)rs, uv, kap, us);
-        const int c[3] = {gx, gy, 0};
-        const T v[4] = {rs, nux, nuy, T(0)};
-        push_boundary<T, 2>(g, a.bc, c, v, [&](const int p[3], const T pv[4]) {
-            const long long pi = p[0] + p[1] * g.sy;
-            a.rout[pi] = pv[0];
-            a.uout[0][pi] = pv[1];
-            a.uout[1][pi] = pv[2];
-            if (obj_on && (!a.obj.mask || a.obj.mask[pi])) {
-                const T pu[3] = {pv[1], pv[2], T(0)}, z3[3] = {0, 0, 0};
-                jacc += obj_density<T>(a.obj, p[0], p[1], 0, (double)pv[0], pu, T(0), z3);
-            }
-        });
+    const int nstrips = (nx + SW - 1) / SW;
+    if (strip >= nstrips) {
+        if (obj_on && lane == 0) a.obj.partials[pslot] = 0.0;
+        return;
     }
-    if (obj_on) store_partial(a.obj, jacc, blin, sh4);
+    const int c = strip * SW - 2 + lane;
+    int cw = c;
+    const bool cin = wrapc(cw, nx, g.per[0]);
+    const int cmin = strip * SW - 2, cmax = cmin + 63;
+    const bool xface = !g.per[0] && ((cmin <= 0 && 0 <= cmax) || (cmin <= nx - 1 && nx - 1 <= cmax));
+    const bool out_lane = lane >= 2 && lane < 62 && c < nx && !on_face(g, 0, c);
+    const int y0 = by * RY;
+    const T *__restrict__ ux_in = a.uin[0];
+    const T *__restrict__ uy_in = a.uin[1];
+    const T *__restrict__ r_in = a.rin;
+    // does this wave's rectangle meet the footprint box (wave-uniform)?
+    const bool wbox = a.m.hi[0] >= strip * SW && a.m.lo[0] < strip * SW + SW && a.m.hi[1] >= y0 &&
+                      a.m.lo[1] < y0 + RY;
+
+    // every row this wave needs, requested before any arithmetic
+    T ux[RY + 5], uy[RY + 5], rv[RY + 2];
+    T kb[RY], sbx[RY], sby[RY];  // kappa, u_S of the output rows (footprint waves only)
+#pragma unroll
+    for (int k = 0; k < RY; ++k) {
+        kb[k] = sbx[k] = sby[k] = T(0);
+        const int o = y0 + k;
+        if (wbox && c >= a.m.lo[0] && c <= a.m.hi[0] && o >= a.m.lo[1] && o <= a.m.hi[1]) {
+            const long long bi = box_index(a.box, a.m, 2, c, o, 0);
+            kb[k] = a.kin[bi];
+            sbx[k] = a.usin[0][bi];
+            sby[k] = a.usin[1][bi];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < RY + 5; ++k) {
+        int yw = y0 - 3 + k;
+        ux[k] = uy[k] = T(0);
+        if (cin && wrapc(yw, ny, g.per[1])) {
+            const long long idx = cw + yw * g.sy;
+            ux[k] = ux_in[idx];
+            uy[k] = uy_in[idx];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < RY + 2; ++k) {
+        int yw = y0 - 1 + k;
+        rv[k] = T(0);
+        if (cin && wrapc(yw, ny, g.per[1])) rv[k] = r_in[cw + yw * g.sy];
+    }
+
+    T acc_r[3] = {0, 0, 0}, acc_m[3] = {0, 0, 0};  // own column: rho*, m_y* for rows r-1, r, r+1
+    T trr[3] = {0, 0, 0}, trm[3] = {0, 0, 0};      // pulled by column c+1
+    T tlr[3] = {0, 0, 0}, tlm[3] = {0, 0, 0};      // pulled by column c-1
+    double jacc = 0.0;
+    const T A2 = T(2) * a.A;
+    const T wa = T(d2q9::WA), wd = T(d2q9::WD), w0 = T(d2q9::W0);
+
+#pragma unroll
+    for (int e = 0; e < RY + 2; ++e) {
+        const int r = y0 - 1 + e;  // row of the E_i evaluated now; u rows r-2..r+2 = ux[e..e+4]
+        int rw = r;
+        if (wrapc(rw, ny, g.per[1])) {  // wave-uniform
+            const T uxc = ux[e + 2], uyc = uy[e + 2];
+            const T uxl = from_left(uxc), uxr = from_right(uxc);
+            const T uyl = from_left(uyc), uyr = from_right(uyc);
+            T dxux = T(0.5) * (uxr - uxl), dxuy = T(0.5) * (uyr - uyl);
+            if (xface) {
+                const T uxll = from_left(uxl), uxrr = from_right(uxr);
+                const T uyll = from_left(uyl), uyrr = from_right(uyr);
+                if (c == 0) {
+                    dxux = T(-1.5) * uxc + T(2) * uxr - T(0.5) * uxrr;
+                    dxuy = T(-1.5) * uyc + T(2) * uyr - T(0.5) * uyrr;
+                } else if (c == nx - 1) {
+                    dxux = T(1.5) * uxc - T(2) * uxl + T(0.5) * uxll;
+                    dxuy = T(1.5) * uyc - T(2) * uyl + T(0.5) * uyll;
+                }
+            }
+            T dyux, dyuy;
+            if (!g.per[1] && rw == 0) {
+                dyux = T(-1.5) * uxc + T(2) * ux[e + 3] - T(0.5) * ux[e + 4];
+                dyuy = T(-1.5) * uyc + T(2) * uy[e + 3] - T(0.5) * uy[e + 4];
+            } else if (!g.per[1] && rw == ny - 1) {
+                dyux = T(1.5) * uxc - T(2) * ux[e + 1] + T(0.5) * ux[e];
+                dyuy = T(1.5) * uyc - T(2) * uy[e + 1] + T(0.5) * uy[e];
+            } else {
+                dyux = T(0.5) * (ux[e + 3] - ux[e + 1]);
+                dyuy = T(0.5) * (uy[e + 3] - uy[e + 1]);
+            }
+            const T a0 = rv[e] - T(1.5) * (uxc * uxc + uyc * uyc);
+            const T bx3 = T(3) * uxc, by3 = T(3) * uyc;
+            const T txx = T(4.5) * uxc * uxc + A2 * dxux;
+            const T tyy = T(4.5) * uyc * uyc + A2 * dyuy;
+            const T txy2 = T(9) * uxc * uyc + A2 * (dyux + dxuy);
+            const T q = a0 + txx + tyy;
+            const T m = cin ? T(1) : T(0);  // nothing from columns outside the domain
+            const T e0 = m * w0 * a0;
+            const T e1 = m * wa * (a0 + bx3 + txx), e3 = m * wa * (a0 - bx3 + txx);
+            const T e2 = m * wa * (a0 + by3 + tyy), e4 = m * wa * (a0 - by3 + tyy);
+            const T e5 = m * wd * (q + bx3 + by3 + txy2), e6 = m * wd * (q - bx3 + by3 - txy2);
+            const T e7 = m * wd * (q - bx3 - by3 + txy2), e8 = m * wd * (q + bx3 - by3 - txy2);
+            acc_r[1] += e0;
+            acc_r[2] += e2;
+            acc_m[2] += e2;
+            acc_r[0] += e4;
+            acc_m[0] -= e4;
+            trr[1] += e1;
+            trr[2] += e5;
+            trm[2] += e5;
+            trr[0] += e8;
+            trm[0] -= e8;
+            tlr[1] += e3;
+            tlr[2] += e6;
+            tlm[2] += e6;
+            tlr[0] += e7;
+            tlm[0] -= e7;
+        }
+        if (e >= 2) {  // output row o = r - 1 (rows y0 .. y0 + RY - 1) is complete
+            const int o = r - 1;
+            const T fr = from_left(trr[0]), fm = from_left(trm[0]);
+            const T gr = from_right(tlr[0]), gm = from_right(tlm[0]);
+            if (out_lane && o < ny && !on_face(g, 1, o)) {
+                const T rs = acc_r[0] + fr + gr, mx = fr - gr, my = acc_m[0] + fm + gm;
+                const T kap = kb[e - 2];
+                const T us0 = sbx[e - 2], us1 = sby[e - 2];
+                const long long idx = c + o * g.sy;
+                const T ks = a.kstatic ? a.kstatic[idx] : T(0);
+                const T inv = T(1) / (T(1) + kap + ks);
+                const T nux = (mx + kap * us0 + a.gf[0]) * inv;
+                const T nuy = (my + kap * us1 + a.gf[1]) * inv;
+                a.rout[idx] = rs;
+                a.uout[0][idx] = nux;
+                a.uout[1][idx] = nuy;
+                if (obj_on && (kap != T(0) || !obj_uses_kappa(a.obj.kind)) && (!a.obj.mask || a.obj.mask[idx])) {
+                    const T uv[3] = {nux, nuy, T(0)}, usv[3] = {us0, us1, T(0)};
+                    jacc += obj_density<T>(a.obj, c, o, 0, (double)rs, uv, kap, usv);
+                }
+                if (c == 1 || c == nx - 2 || o == 1 || o == ny - 2)
+                    jacc += fwd2d_push<T>(a, c, o, rs, nux, nuy, obj_on);
+            }
+        }
+        acc_r[0] = acc_r[1]; acc_r[1] = acc_r[2]; acc_r[2] = T(0);
+        acc_m[0] = acc_m[1]; acc_m[1] = acc_m[2]; acc_m[2] = T(0);
+        trr[0] = trr[1]; trr[1] = trr[2]; trr[2] = T(0);
+        trm[0] = trm[1]; trm[1] = trm[2]; trm[2] = T(0);
+        tlr[0] = tlr[1]; tlr[1] = tlr[2]; tlr[2] = T(0);
+        tlm[0] = tlm[1]; tlm[1] = tlm[2]; tlm[2] = T(0);
+    }
+    if (obj_on) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) jacc += __shfl_xor(jacc, o, 64);
+        if (lane == 0) a.obj.partials[pslot] = jacc;
+    }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_fwd2d(const FwdArgs<T> a) {
-    fwd2d_body<T>(a, blockIdx.x, blockIdx.y, blockIdx.x + (long long)blockIdx.y * gridDim.x);
+__host__ __device__ inline int fwd2d_grid_x(const Geom &g) {
+    const int nstrips = (g.n[0] + SW - 1) / SW;
+    return (nstrips + WPB - 1) / WPB;
 }
+__host__ __device__ inline int fwd2d_grid_y(const Geom &g) { return (g.n[1] + RY - 1) / RY; }
 
 // first tile of the job that owns flat tile b (tile0 ascending, tile0[0] = 0)
 __device__ __forceinline__ int job_of(const long long *tile0, int njobs, long long b) {
@@ -180,7 +263,6 @@ __device__ __forceinline__ int job_of(const long long *tile0, int njobs, long lo
     return lo;
 }
 
-// one launch for the current step of many jobs: flat tile b -> (job, local tile)
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fwd2d_batch(const FwdArgs<T> *args, const long long *tile0,
                                                         int njobs) {
@@ -188,8 +270,13 @@ __global__ __launch_bounds__(kBlock) void k_fwd2d_batch(const FwdArgs<T> *args, 
     const int j = job_of(tile0, njobs, b);
     const FwdArgs<T> &a = args[j];
     const long long t = b - tile0[j];
-    const int nbx = (a.g.n[0] + TX - 1) / TX;
-    fwd2d_body<T>(a, (int)(t % nbx), (int)(t / nbx), t);
+    const long long ns = (a.mode & FWD_STENCIL) ? (long long)fwd2d_grid_x(a.g) * fwd2d_grid_y(a.g) : 0;
+    if (t >= ns) {  // extra blocks: transfer of the next step onto its footprint box
+        transfer_box<T, 2, kBlock>(a.des, a.mnext, a.box, a.knext, a.usnext, t - ns);
+        return;
+    }
+    const int nbx = fwd2d_grid_x(a.g);
+    fwd2d_body<T>(a, (int)(t % nbx), (int)(t / nbx), t * WPB);
 }
 
 // transposed difference operator along one axis at coordinate c: sum_r D[r][c] f(r), with f
@@ -370,11 +457,6 @@ __device__ __forceinline__ void adj2d_body(const AdjArgs<T> &a, int bx, int by) 
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_adj2d(const AdjArgs<T> a) {
-    adj2d_body<T>(a, blockIdx.x, blockIdx.y);
-}
-
-template <typename T>
 __global__ __launch_bounds__(kBlock) void k_adj2d_batch(const AdjArgs<T> *args, const long long *tile0,
                                                         int njobs) {
     const long long b = blockIdx.x;
@@ -385,25 +467,18 @@ __global__ __launch_bounds__(kBlock) void k_adj2d_batch(const AdjArgs<T> *args, 
     adj2d_body<T>(a, (int)(t % nbx), (int)(t / nbx));
 }
 
-template <typename T>
-hipError_t launch_fwd2d(const FwdArgs<T> &a, hipStream_t s) {
-    dim3 grid((a.g.n[0] + TX - 1) / TX, (a.g.n[1] + TY - 1) / TY);
-    hipLaunchKernelGGL(k_fwd2d<T>, grid, dim3(kBlock), 0, s, a);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_adj2d(const AdjArgs<T> &a, hipStream_t s) {
-    dim3 grid((a.g.n[0] + TX - 1) / TX, (a.g.n[1] + TY - 1) / TY);
-    hipLaunchKernelGGL(k_adj2d<T>, grid, dim3(kBlock), 0, s, a);
-    return hipGetLastError();
-}
-
 long long fwd_blocks(const Geom &g, int lattice, int esz) {
-    if (g.dim == 2) return (long long)((g.n[0] + TX - 1) / TX) * ((g.n[1] + TY - 1) / TY);
+    // one objective partial per wave (2D) or per block (3D)
+    if (g.dim == 2) return (long long)fwd2d_grid_x(g) * fwd2d_grid_y(g) * WPB;
     return fwd_blocks3d(g, lattice, esz);
 }
 
+long long xfer_blocks(int dim, long long cells, int esz) {
+    if (dim == 2) return (cells + kBlock - 1) / kBlock;
+    return xfer_blocks3d(cells, esz);
+}
+
+long long tiles2d_fwd(const Geom &g) { return (long long)fwd2d_grid_x(g) * fwd2d_grid_y(g); }
 long long tiles2d(const Geom &g) { return (long long)((g.n[0] + TX - 1) / TX) * ((g.n[1] + TY - 1) / TY); }
 
 template <typename T>
@@ -425,9 +500,5 @@ template hipError_t launch_fwd2d_batch<double>(const FwdArgs<double> *, const lo
 template hipError_t launch_adj2d_batch<float>(const AdjArgs<float> *, const long long *, int, long long, hipStream_t);
 template hipError_t launch_adj2d_batch<double>(const AdjArgs<double> *, const long long *, int, long long, hipStream_t);
 
-template hipError_t launch_fwd2d<float>(const FwdArgs<float> &, hipStream_t);
-template hipError_t launch_fwd2d<double>(const FwdArgs<double> &, hipStream_t);
-template hipError_t launch_adj2d<float>(const AdjArgs<float> &, hipStream_t);
-template hipError_t launch_adj2d<double>(const AdjArgs<double> &, hipStream_t);
 
 }  // namespace lks

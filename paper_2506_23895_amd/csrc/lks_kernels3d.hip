@@ -215,8 +215,13 @@ __device__ __forceinline__ void fwd3d_body(const FwdArgs<T> &a, int bx, int by, 
             !on_face(g, 2, zo)) {
             const T rs = acc[0][0];
             T kap = 0, us[3] = {0, 0, 0};
-            const bool inb = in_box(a.m, 3, gx, gy, zo);
-            if (inb) gather_kappa<T, 3>(a.des, a.m, gx, gy, zo, kap, us);
+            if (in_box(a.m, 3, gx, gy, zo)) {
+                const long long bi = box_index(a.box, a.m, 3, gx, gy, zo);
+                kap = a.kin[bi];
+                us[0] = a.usin[0][bi];
+                us[1] = a.usin[1][bi];
+                us[2] = a.usin[2][bi];
+            }
             const long long idx = gx + gy * g.sy + zo * g.sz;
             const T ks = a.kstatic ? a.kstatic[idx] : T(0);
             const T inv = T(1) / (T(1) + kap + ks);
@@ -227,13 +232,6 @@ __device__ __forceinline__ void fwd3d_body(const FwdArgs<T> &a, int bx, int by, 
             a.uout[0][idx] = nu[0];
             a.uout[1][idx] = nu[1];
             a.uout[2][idx] = nu[2];
-            if (a.kbox && inb) {
-                const long long bi = box_index(a.box, a.m, 3, gx, gy, zo);
-                a.kbox[bi] = kap;
-                a.usbox[0][bi] = us[0];
-                a.usbox[1][bi] = us[1];
-                a.usbox[2][bi] = us[2];
-            }
             if (obj_on && (!a.obj.mask || a.obj.mask[idx]))
                 jacc += obj_density<T>(a.obj, gx, gy, zo, (double)rs, nu, kap, us);
             const int c3[3] = {gx, gy, zo};
@@ -261,12 +259,6 @@ __device__ __forceinline__ void fwd3d_body(const FwdArgs<T> &a, int bx, int by, 
     if (obj_on) store_partial<NT>(a.obj, jacc, blin, sh);
 }
 
-template <typename T, int Q>
-__global__ __launch_bounds__(Tile3<T>::TX * Tile3<T>::TY) void k_fwd3d(const FwdArgs<T> a) {
-    fwd3d_body<T, Q>(a, blockIdx.x, blockIdx.y, blockIdx.z,
-                     blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z));
-}
-
 __device__ __forceinline__ int job_of3(const long long *tile0, int njobs, long long b) {
     int lo = 0, hi = njobs - 1;
     while (lo < hi) {
@@ -286,6 +278,12 @@ __device__ __forceinline__ void tile_coords3(const Geom &g, long long t, int &bx
     bz = (int)(t / ((long long)nbx * nby));
 }
 
+template <typename T>
+__device__ __forceinline__ long long stencil_tiles3(const Geom &g) {
+    return (long long)((g.n[0] + Tile3<T>::TX - 1) / Tile3<T>::TX) *
+           ((g.n[1] + Tile3<T>::TY - 1) / Tile3<T>::TY) * ((g.n[2] + Tile3<T>::ZC - 1) / Tile3<T>::ZC);
+}
+
 template <typename T, int Q>
 __global__ __launch_bounds__(Tile3<T>::TX * Tile3<T>::TY) void k_fwd3d_batch(const FwdArgs<T> *args,
                                                                             const long long *tile0,
@@ -294,6 +292,11 @@ __global__ __launch_bounds__(Tile3<T>::TX * Tile3<T>::TY) void k_fwd3d_batch(con
     const int j = job_of3(tile0, njobs, b);
     const FwdArgs<T> &a = args[j];
     const long long t = b - tile0[j];
+    const long long ns = (a.mode & FWD_STENCIL) ? stencil_tiles3<T>(a.g) : 0;
+    if (t >= ns) {  // extra blocks: transfer of the next step onto its footprint box
+        transfer_box<T, 3, Tile3<T>::TX * Tile3<T>::TY>(a.des, a.mnext, a.box, a.knext, a.usnext, t - ns);
+        return;
+    }
     int bx, by, bz;
     tile_coords3<T>(a.g, t, bx, by, bz);
     fwd3d_body<T, Q>(a, bx, by, bz, t);
@@ -380,11 +383,6 @@ __device__ __forceinline__ void adj3d_prep_body(const AdjArgs<T> &a, long long b
             kb += a.obj.scale * obj_dkappa(a.obj, x, y, z, uu, uss);
         a.kbar[bi] = (T)kb;
     }
-}
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_adj3d_prep(const AdjArgs<T> a) {
-    adj3d_prep_body<T>(a, blockIdx.x);
 }
 
 template <typename T>
@@ -583,11 +581,6 @@ __device__ __forceinline__ void adj3d_main_body(const AdjArgs<T> &a, int bx, int
 }
 
 template <typename T, int Q>
-__global__ __launch_bounds__(Tile3<T>::TX * Tile3<T>::TY) void k_adj3d_main(const AdjArgs<T> a) {
-    adj3d_main_body<T, Q>(a, blockIdx.x, blockIdx.y, blockIdx.z);
-}
-
-template <typename T, int Q>
 __global__ __launch_bounds__(Tile3<T>::TX * Tile3<T>::TY) void k_adj3d_main_batch(const AdjArgs<T> *args,
                                                                                  const long long *tile0,
                                                                                  int njobs) {
@@ -607,32 +600,12 @@ long long fwd_blocks3d(const Geom &g, int lattice, int esz) {
     return (long long)((g.n[0] + TX - 1) / TX) * ((g.n[1] + TY - 1) / TY) * ((g.n[2] + ZC - 1) / ZC);
 }
 
-template <typename T>
-static dim3 grid3(const Geom &g) {
-    return dim3((g.n[0] + Tile3<T>::TX - 1) / Tile3<T>::TX, (g.n[1] + Tile3<T>::TY - 1) / Tile3<T>::TY,
-                (g.n[2] + Tile3<T>::ZC - 1) / Tile3<T>::ZC);
-}
-
-template <typename T>
-hipError_t launch_fwd3d(const FwdArgs<T> &a, int lattice, hipStream_t s) {
-    const dim3 blk(Tile3<T>::TX * Tile3<T>::TY);
-    if (lattice == 2) hipLaunchKernelGGL((k_fwd3d<T, 19>), grid3<T>(a.g), blk, 0, s, a);
-    else hipLaunchKernelGGL((k_fwd3d<T, 15>), grid3<T>(a.g), blk, 0, s, a);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_adj3d(const AdjArgs<T> &a, int lattice, hipStream_t s) {
-    const long long ncell = (long long)a.g.n[0] * a.g.n[1] * a.g.n[2];
-    hipLaunchKernelGGL(k_adj3d_prep<T>, dim3((unsigned)((ncell + kBlock - 1) / kBlock)), dim3(kBlock),
-                       0, s, a);
-    const dim3 blk(Tile3<T>::TX * Tile3<T>::TY);
-    if (lattice == 2) hipLaunchKernelGGL((k_adj3d_main<T, 19>), grid3<T>(a.g), blk, 0, s, a);
-    else hipLaunchKernelGGL((k_adj3d_main<T, 15>), grid3<T>(a.g), blk, 0, s, a);
-    return hipGetLastError();
-}
-
 long long tiles3d(const Geom &g, int esz) { return fwd_blocks3d(g, 0, esz); }
+
+long long xfer_blocks3d(long long cells, int esz) {
+    const long long nt = esz == 8 ? Tile3<double>::TX * Tile3<double>::TY : Tile3<float>::TX * Tile3<float>::TY;
+    return (cells + nt - 1) / nt;
+}
 
 template <typename T>
 hipError_t launch_fwd3d_batch(const FwdArgs<T> *args, const long long *tile0, int njobs,
@@ -664,10 +637,5 @@ hipError_t launch_adj3d_batch(const AdjArgs<T> *args, const long long *blk0, lon
 LKS_INST3(float)
 LKS_INST3(double)
 #undef LKS_INST3
-
-template hipError_t launch_fwd3d<float>(const FwdArgs<float> &, int, hipStream_t);
-template hipError_t launch_fwd3d<double>(const FwdArgs<double> &, int, hipStream_t);
-template hipError_t launch_adj3d<float>(const AdjArgs<float> &, int, hipStream_t);
-template hipError_t launch_adj3d<double>(const AdjArgs<double> &, int, hipStream_t);
 
 }  // namespace lks

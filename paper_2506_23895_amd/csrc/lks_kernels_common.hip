@@ -71,26 +71,35 @@ __device__ __forceinline__ void sens_body(const SensArgs<T> &a, long long blk) {
         lo[r] = max(a.m.lo[r], (int)ceil(xr[r] - s));
         hi[r] = min(a.m.hi[r], (int)floor(xr[r] + s));
     }
+    // the weight is a product over analysis axes and the support spans at most 2s + 1 nodes per
+    // axis: per-axis weights first, then every load of a z-plane issued together
+    constexpr int MW = 5;
+    T wx[MW], wy[MW];
+#pragma unroll
+    for (int t = 0; t < MW; ++t) {
+        wx[t] = lo[0] + t <= hi[0] ? wk<T>(a.des.weight, (T)(lo[0] + t - xr[0])) : T(0);
+        wy[t] = lo[1] + t <= hi[1] ? wk<T>(a.des.weight, (T)(lo[1] + t - xr[1])) : T(0);
+    }
     double acc = 0.0;
     for (int z = lo[2]; z <= hi[2]; ++z) {
         const T wz = (a.dim == 3) ? wk<T>(a.des.weight, (T)(z - xr[2])) : T(1);
         if (wz == T(0)) continue;
-        for (int y = lo[1]; y <= hi[1]; ++y) {
-            const T wy = wk<T>(a.des.weight, (T)(y - xr[1]));
-            if (wy == T(0)) continue;
-            for (int x = lo[0]; x <= hi[0]; ++x) {
-                const T wx = wk<T>(a.des.weight, (T)(x - xr[0]));
-                if (wx == T(0)) continue;
-                acc += (double)(wx * wy * wz) * (double)a.kbar[box_index(a.box, a.m, a.dim, x, y, z)];
-            }
-        }
+        T kv[MW][MW];
+#pragma unroll
+        for (int ty = 0; ty < MW; ++ty)
+#pragma unroll
+            for (int tx = 0; tx < MW; ++tx)
+                kv[ty][tx] = (wx[tx] != T(0) && wy[ty] != T(0))
+                                 ? a.kbar[box_index(a.box, a.m, a.dim, lo[0] + tx, lo[1] + ty, z)]
+                                 : T(0);
+#pragma unroll
+        for (int ty = 0; ty < MW; ++ty)
+#pragma unroll
+            for (int tx = 0; tx < MW; ++tx)
+                if (wx[tx] != T(0) && wy[ty] != T(0))
+                    acc += (double)(wx[tx] * wy[ty] * wz) * (double)kv[ty][tx];
     }
     a.G[i] += acc;
-}
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_sens(const SensArgs<T> a) {
-    sens_body<T>(a, blockIdx.x);
 }
 
 template <typename T>
@@ -155,13 +164,6 @@ hipError_t launch_init(const InitArgs<T> &a, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_sens(const SensArgs<T> &a, hipStream_t s) {
-    const long long ndn = (long long)a.des.nd[0] * a.des.nd[1] * a.des.nd[2];
-    hipLaunchKernelGGL(k_sens<T>, grid1(ndn), dim3(kBlock), 0, s, a);
-    return hipGetLastError();
-}
-
-template <typename T>
 hipError_t launch_sens_batch(const SensArgs<T> *args, const long long *blk0, int njobs, long long nblk,
                              hipStream_t s) {
     if (njobs == 0) return hipSuccess;
@@ -202,7 +204,6 @@ hipError_t launch_reduce_steps(const double *partials, long long stride, long lo
     template hipError_t launch_design_prep<T>(const T *, T *, double *, long long, int, double,   \
                                               double, hipStream_t);                               \
     template hipError_t launch_init<T>(const InitArgs<T> &, hipStream_t);                         \
-    template hipError_t launch_sens<T>(const SensArgs<T> &, hipStream_t);                         \
     template hipError_t launch_sens_batch<T>(const SensArgs<T> *, const long long *, int, long long, \
                                              hipStream_t);                                        \
     template hipError_t launch_sens_finish<T>(const double *, const double *, T *, long long,     \
