@@ -25,6 +25,7 @@ using lks::StepMotion;
 namespace {
 
 thread_local std::string g_create_error;
+constexpr int kPartialRows = 64;
 
 const char *kind_name(int k) {
     switch (k) {
@@ -51,6 +52,9 @@ struct Layout {
     size_t b_state = 0, b_ckpt = 0, b_traj = 0, b_box = 0, b_kbar = 0, b_adj = 0, b_design = 0,
            b_aux = 0, b_final = 0, b_pv = 0, b_args = 0, b_xring = 0;
     long long max_blocks = 0;
+    int prow = 1;            // rows of the objective-partials ring (steps reduced per batch)
+    int banks = 1;           // trajectory/box store banks: 2 lets a segment be recomputed while
+                             // the adjoint of the following one runs
     bool fwd_only = false;   // objective NONE: forward sweep only, no trajectory or adjoint storage
 };
 
@@ -127,6 +131,7 @@ int plan(const lks_desc *d, Layout &L, std::string *err) {
     L.fwd_only = d->objective.kind == LKS_OBJ_NONE;  // nothing to differentiate: no reverse buffers
     L.K = (L.fwd_only || d->checkpoint_every == 0 || d->checkpoint_every >= N) ? N : d->checkpoint_every;
     L.S = (N + L.K - 1) / L.K;
+    L.banks = (!L.fwd_only && L.S > 1) ? 2 : 1;
 
     // rigid motion: orthogonal R; 2D motion stays in the plane; footprint inside the domain
     const double s = d->weight == LKS_W_LIN ? 1.0 : 2.0;
@@ -193,8 +198,8 @@ int plan(const lks_desc *d, Layout &L, std::string *err) {
     const size_t nf = 1 + D;
     L.b_state = 2 * nf * L.F * e;
     L.b_ckpt = (size_t)L.S * nf * L.F * e;
-    L.b_traj = L.fwd_only ? 0 : (size_t)(L.K + 1) * D * L.F * e;
-    L.b_box = L.fwd_only ? 0 : (size_t)L.K * nf * L.box.cells * e;
+    L.b_traj = L.fwd_only ? 0 : (size_t)L.banks * (L.K + 1) * D * L.F * e;
+    L.b_box = L.fwd_only ? 0 : (size_t)L.banks * L.K * nf * L.box.cells * e;
     L.b_xring = 2 * nf * L.box.cells * e;  // kappa, u_S of the steps outside the stored segment
     L.b_kbar = L.fwd_only ? 0 : (size_t)L.box.cells * e;
     L.b_adj = L.fwd_only ? 0 : 2 * nf * L.F * e;
@@ -202,9 +207,11 @@ int plan(const lks_desc *d, Layout &L, std::string *err) {
     L.b_design = (size_t)L.nd * (3 * e + 2 * 8);  // gamma, kref, sens out; kprime, G
     L.max_blocks = lks::fwd_blocks(g, d->lattice, (int)L.esz);
     L.b_pv = (D == 3 && !L.fwd_only) ? (size_t)4 * L.F * e : 0;  // (P*, V*) between the 3D adjoint kernels
-    // objective partials: one row of per-block sums per step of the window, reduced at the end
+    // objective partials: a ring of rows of per-wave (2D) or per-block (3D) sums, one row per step,
+    // reduced into j^n every kPartialRows steps of the window and at its end
     const long long obj_rows = d->objective.kind == LKS_OBJ_NONE ? 1 : (d->objective.n1 - d->objective.n0 + 1);
-    L.b_aux = (size_t)(d->nsteps + 1) * 8 + (size_t)obj_rows * L.max_blocks * 8 + 64;
+    L.prow = (int)std::min<long long>(obj_rows, kPartialRows);
+    L.b_aux = (size_t)(d->nsteps + 1) * 8 + (size_t)L.prow * L.max_blocks * 8 + 64;
     if (d->kappa_static) L.b_aux += L.F * e;
     if (d->objective.kind != LKS_OBJ_NONE && d->objective.mask) L.b_aux += L.F;
     if (d->rho_init || d->u_init) L.b_aux += nf * L.F * e;
@@ -263,6 +270,9 @@ struct lks_ctx {
     long long *tile0 = nullptr; // device {0}: the single job of a one-job launch
     void *out_dev = nullptr;    // caller's device buffer for dJ/dgamma
     hipEvent_t done_ev = nullptr;
+    // reverse sweep: segments are recomputed on stream2 while the adjoint runs on stream
+    hipStream_t stream2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_rec = nullptr, ev_adj = nullptr;
 
     size_t esz() const { return L.esz; }
     int D() const { return d.dim; }
@@ -329,14 +339,24 @@ lks::ObjParams obj_params(const lks_ctx *c, int n) {
         o.dir[a] = ob.dir[a];
     }
     o.mask = c->mask;
-    o.partials = o.active ? c->partials + (long long)(n - ob.n0) * c->L.max_blocks : nullptr;
+    o.partials = o.active ? c->partials + (long long)((n - ob.n0) % c->L.prow) * c->L.max_blocks : nullptr;
     return o;
+}
+
+// After forward step n: first step of the run of partial rows to reduce now (the ring is full or
+// the window ends), or 0.
+int reduce_from(const lks_ctx *c, int n) {
+    const lks_objective &ob = c->d.objective;
+    if (ob.kind == LKS_OBJ_NONE || n < ob.n0 || n > ob.n1) return 0;
+    const int k = (n - ob.n0) % c->L.prow;
+    return (k == c->L.prow - 1 || n == ob.n1) ? n - k : 0;
 }
 
 // ---- timing: sample every k-th launch of a kernel kind with an event pair ------------------
 int flush_timing(lks_ctx *c) {
     if (c->pool_used == 0) return LKS_OK;
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->stream2) HIPCHK(c, hipStreamSynchronize(c->stream2));
     for (size_t i = 0; i < c->pool_used; ++i) {
         float ms = 0;
         HIPCHK(c, hipEventElapsedTime(&ms, c->pool[i].a, c->pool[i].b));
@@ -350,38 +370,48 @@ int flush_timing(lks_ctx *c) {
 struct Timed {
     lks_ctx *c;
     EventPair *ev = nullptr;
-    Timed(lks_ctx *cc, int kind) : c(cc) {
+    hipStream_t s;
+    Timed(lks_ctx *cc, int kind, hipStream_t st) : c(cc), s(st) {
         const long k = c->launches[kind]++;
         if (c->every > 0 && k % c->every == 0 && c->pool_used < c->pool.size()) {
             ev = &c->pool[c->pool_used++];
             ev->kind = kind;
-            (void)hipEventRecord(ev->a, c->stream);
+            (void)hipEventRecord(ev->a, s);
         }
     }
     ~Timed() {
-        if (ev) (void)hipEventRecord(ev->b, c->stream);
+        if (ev) (void)hipEventRecord(ev->b, s);
         if (ev && c->pool_used == c->pool.size()) (void)flush_timing(c);
     }
 };
+
+// Segment seg keeps its trajectory and footprint arrays in bank (S - 1 - seg) % 2: the last
+// segment (written by the forward sweep) is in bank 0, and consecutive segments alternate, so
+// segment seg - 1 can be recomputed while the adjoint of segment seg reads the other bank.
+int bank_of(const lks_ctx *c, int seg) { return c->L.banks == 1 ? 0 : (c->L.S - 1 - seg) & 1; }
 
 // kappa and u_S of one step on its footprint box: (1 + dim) arrays of box.cells values.  The
 // forward sweep keeps them in a two-slot ring (step n in slot n % 2) except in the last segment,
 // whose steps go to the box store (slot j - 1 for the j-th step of the segment) because the
 // reverse sweep reads them; a recomputed segment writes the box store the same way.
 template <typename T>
-T *box_slot(lks_ctx *c, bool ring, int slot) {
-    return reinterpret_cast<T *>(ring ? c->xring : c->box) + (long long)slot * (1 + c->d.dim) * c->L.box.cells;
+T *box_slot(lks_ctx *c, bool ring, int slot, int bank = 0) {
+    const long long s = ring ? slot : (long long)bank * c->L.K + slot;
+    return reinterpret_cast<T *>(ring ? c->xring : c->box) + s * (1 + c->d.dim) * c->L.box.cells;
 }
 
 template <typename T>
 T *fwd_loc(lks_ctx *c, int n) {
     const int seg = (n - 1) / c->L.K;
-    if (seg == c->L.S - 1 && !c->L.fwd_only) return box_slot<T>(c, false, n - seg * c->L.K - 1);
+    if (seg == c->L.S - 1 && !c->L.fwd_only)
+        return box_slot<T>(c, false, n - seg * c->L.K - 1, bank_of(c, seg));
     return box_slot<T>(c, true, n & 1);
 }
 
 template <typename T>
-T *rec_loc(lks_ctx *c, int seg, int n) { return box_slot<T>(c, false, n - seg * c->L.K - 1); }
+T *rec_loc(lks_ctx *c, int seg, int n) {
+    return box_slot<T>(c, false, n - seg * c->L.K - 1, bank_of(c, seg));
+}
 
 template <typename T>
 lks::FwdArgs<T> base_fwd_args(lks_ctx *c) {
@@ -446,18 +476,18 @@ long long fwd_tiles(const lks_ctx *c, int mode) {
 
 // one-job launches: the argument block lives in device memory (see upload_args)
 template <typename T>
-hipError_t launch_fwd_raw(lks_ctx *c, const lks::FwdArgs<T> *dargs, long long ntiles) {
-    return c->d.dim == 2 ? lks::launch_fwd2d_batch<T>(dargs, c->tile0, 1, ntiles, c->stream)
-                         : lks::launch_fwd3d_batch<T>(dargs, c->tile0, 1, ntiles, c->d.lattice, c->stream);
+hipError_t launch_fwd_raw(lks_ctx *c, const lks::FwdArgs<T> *dargs, long long ntiles, hipStream_t s) {
+    return c->d.dim == 2 ? lks::launch_fwd2d_batch<T>(dargs, c->tile0, 1, ntiles, s)
+                         : lks::launch_fwd3d_batch<T>(dargs, c->tile0, 1, ntiles, c->d.lattice, s);
 }
 
 // one forward step (timed as kind 0); mode is the host copy's mode
 template <typename T>
-int launch_fwd_dev(lks_ctx *c, const lks::FwdArgs<T> *dargs, int mode) {
+int launch_fwd_dev(lks_ctx *c, const lks::FwdArgs<T> *dargs, int mode, hipStream_t s) {
     hipError_t e;
     {
-        Timed t(c, 0);
-        e = launch_fwd_raw<T>(c, dargs, fwd_tiles(c, mode));
+        Timed t(c, 0, s);
+        e = launch_fwd_raw<T>(c, dargs, fwd_tiles(c, mode), s);
     }
     HIPCHK(c, e);
     return LKS_OK;
@@ -465,8 +495,8 @@ int launch_fwd_dev(lks_ctx *c, const lks::FwdArgs<T> *dargs, int mode) {
 
 // transfer-only launch (not part of the per-step timing)
 template <typename T>
-int launch_xfer_dev(lks_ctx *c, const lks::FwdArgs<T> *dargs) {
-    HIPCHK(c, (launch_fwd_raw<T>(c, dargs, fwd_tiles(c, lks::FWD_TRANSFER_NEXT))));
+int launch_xfer_dev(lks_ctx *c, const lks::FwdArgs<T> *dargs, hipStream_t s) {
+    HIPCHK(c, (launch_fwd_raw<T>(c, dargs, fwd_tiles(c, lks::FWD_TRANSFER_NEXT), s)));
     return LKS_OK;
 }
 
@@ -474,7 +504,7 @@ template <typename T>
 int launch_adj_dev(lks_ctx *c, const lks::AdjArgs<T> *dargs, const lks::SensArgs<T> *dsens) {
     hipError_t e;
     {
-        Timed t(c, 1);
+        Timed t(c, 1, c->stream);
         e = c->d.dim == 2
                 ? lks::launch_adj2d_batch<T>(dargs, c->tile0, 1, lks::tiles2d(c->L.g), c->stream)
                 : lks::launch_adj3d_batch<T>(dargs, c->tile0, (c->L.ncell + lks::kBlockHost - 1) / lks::kBlockHost,
@@ -483,7 +513,7 @@ int launch_adj_dev(lks_ctx *c, const lks::AdjArgs<T> *dargs, const lks::SensArgs
     }
     HIPCHK(c, e);
     {
-        Timed t(c, 2);
+        Timed t(c, 2, c->stream);
         e = lks::launch_sens_batch<T>(dsens, c->tile0, 1, (c->L.nd + lks::kBlockHost - 1) / lks::kBlockHost,
                                       c->stream);
     }
@@ -517,16 +547,16 @@ Fields<T> state_fields(lks_ctx *c, char *base) {  // (1 + dim) consecutive field
 }
 
 template <typename T>
-void traj_slot(lks_ctx *c, int j, T *u[3]) {  // dim consecutive fields per slot
+void traj_slot(lks_ctx *c, int bank, int j, T *u[3]) {  // dim consecutive fields per slot
+    const long long slot = (long long)bank * (c->L.K + 1) + j;
     for (int k = 0; k < 3; ++k)
-        u[k] = k < c->d.dim ? reinterpret_cast<T *>(c->field(c->traj, (long long)j * c->d.dim + k))
-                            : nullptr;
+        u[k] = k < c->d.dim ? reinterpret_cast<T *>(c->field(c->traj, slot * c->d.dim + k)) : nullptr;
 }
 
 template <typename T>
-int copy_fields(lks_ctx *c, T *dst, const T *src, int nfields) {
+int copy_fields(lks_ctx *c, T *dst, const T *src, int nfields, hipStream_t s = nullptr) {
     HIPCHK(c, hipMemcpyAsync(dst, src, (size_t)nfields * c->L.F * sizeof(T), hipMemcpyDeviceToDevice,
-                             c->stream));
+                             s ? s : c->stream));
     return LKS_OK;
 }
 
@@ -568,8 +598,8 @@ int forward_impl(lks_ctx *c, const void *gamma, double *J) {
             const bool last = seg == S - 1 && !L.fwd_only;
             T *uin[3], *uout[3];
             if (last) {
-                traj_slot<T>(c, j - 1, uin);
-                traj_slot<T>(c, j, uout);
+                traj_slot<T>(c, 0, j - 1, uin);
+                traj_slot<T>(c, 0, j, uout);
             } else {
                 for (int k = 0; k < 3; ++k) {
                     uin[k] = st[cur].u[k];
@@ -585,7 +615,7 @@ int forward_impl(lks_ctx *c, const void *gamma, double *J) {
     }
     const auto *dfa = reinterpret_cast<const lks::FwdArgs<T> *>(c->argdev);
     const auto *hfa = reinterpret_cast<const lks::FwdArgs<T> *>(c->arghost);
-    if ((rc = launch_xfer_dev<T>(c, dfa + N))) return rc;
+    if ((rc = launch_xfer_dev<T>(c, dfa + N, c->stream))) return rc;
     int cur = 0;
     for (int n = 1; n <= N; ++n) {
         const int seg = (n - 1) / K, j = n - seg * K;
@@ -598,18 +628,16 @@ int forward_impl(lks_ctx *c, const void *gamma, double *J) {
                 return rc;
             if (last) {
                 T *t0[3];
-                traj_slot<T>(c, 0, t0);
+                traj_slot<T>(c, 0, 0, t0);
                 if ((rc = copy_fields<T>(c, t0[0], st[cur].u[0], D))) return rc;
             }
         }
-        if ((rc = launch_fwd_dev<T>(c, dfa + (n - 1), hfa[n - 1].mode))) return rc;
+        if ((rc = launch_fwd_dev<T>(c, dfa + (n - 1), hfa[n - 1].mode, c->stream))) return rc;
+        if (const int na = reduce_from(c, n))  // j^na .. j^n, each in block order
+            HIPCHK(c, lks::launch_reduce_steps(c->partials, L.max_blocks, L.max_blocks, na, n, c->obj_scale,
+                                               c->jn, c->stream));
         cur = 1 - cur;
     }
-    if (c->d.objective.kind != LKS_OBJ_NONE)  // j^n of every step of the window, in block order
-        HIPCHK(c, lks::launch_reduce_steps(c->partials, L.max_blocks, L.max_blocks,
-                                           c->d.objective.n0,
-                                           c->d.objective.n1, c->obj_scale,
-                                           c->jn + 0, c->stream));
     // keep X^N: the trajectory store is reused by the reverse sweep
     {
         Fields<T> fin = state_fields<T>(c, c->fin);
@@ -617,7 +645,7 @@ int forward_impl(lks_ctx *c, const void *gamma, double *J) {
         if (L.fwd_only) {
             for (int k = 0; k < 3; ++k) ul[k] = st[cur].u[k];
         } else {
-            traj_slot<T>(c, N - (S - 1) * K, ul);
+            traj_slot<T>(c, 0, N - (S - 1) * K, ul);
         }
         if ((rc = copy_fields<T>(c, fin.r, st[cur].r, 1))) return rc;
         if ((rc = copy_fields<T>(c, fin.u[0], ul[0], D))) return rc;
@@ -653,8 +681,9 @@ lks::AdjArgs<T> make_adj_args(lks_ctx *c, int n, int j, int acur) {
     a.Pin = ad[acur].r;
     a.Pout = ad[1 - acur].r;
     T *up[3], *uc[3];
-    traj_slot<T>(c, j - 1, up);
-    traj_slot<T>(c, j, uc);
+    const int bank = bank_of(c, (n - 1) / L.K);
+    traj_slot<T>(c, bank, j - 1, up);
+    traj_slot<T>(c, bank, j, uc);
     for (int k = 0; k < 3; ++k) {
         a.Vin[k] = ad[acur].u[k];
         a.Vout[k] = ad[1 - acur].u[k];
@@ -662,7 +691,7 @@ lks::AdjArgs<T> make_adj_args(lks_ctx *c, int n, int j, int acur) {
         a.ucur[k] = uc[k];
     }
     a.kstatic = reinterpret_cast<const T *>(c->kstatic);
-    const T *b = reinterpret_cast<const T *>(c->box) + (long long)(j - 1) * (1 + D) * L.box.cells;
+    const T *b = box_slot<T>(c, false, j - 1, bank);
     a.kbox = b;
     for (int k = 0; k < 3; ++k) a.usbox[k] = k < D ? b + (1 + k) * L.box.cells : nullptr;
     a.kbar = reinterpret_cast<T *>(c->kbar);
@@ -688,6 +717,11 @@ lks::SensArgs<T> make_sens_args(lks_ctx *c, int n) {
     return sa;
 }
 
+// Reverse sweep, segments last to first.  The adjoint of segment seg runs on the context's
+// stream while segment seg - 1 is restored from its checkpoint and recomputed on stream2 into
+// the other trajectory/footprint bank: the two launch sequences are independent and each is
+// latency-bound, so they share the GPU.  Events order the banks: the recompute of seg - 1 waits
+// for the adjoint of seg + 1 (same bank), the adjoint of seg waits for its recompute.
 template <typename T>
 int adjoint_impl(lks_ctx *c) {
     const Layout &L = c->L;
@@ -695,9 +729,8 @@ int adjoint_impl(lks_ctx *c) {
     int rc;
     Fields<T> st[2] = {state_fields<T>(c, c->state), state_fields<T>(c, c->field(c->state, 1 + D))};
     Fields<T> ad = state_fields<T>(c, c->adj);
-    // argument blocks: recomputed steps (every segment but the last), adjoint steps, gathers
-    // layout: recomputed steps [0, nrec), one transfer-only block per recomputed segment, then
-    // the adjoint steps and the gathers
+    // argument blocks: recomputed steps (every segment but the last), one transfer-only block per
+    // recomputed segment, then the adjoint steps and the gathers
     const int nrec = (S - 1) * K, nfa = nrec + (S - 1);
     auto *ra = reinterpret_cast<lks::FwdArgs<T> *>(c->arghost);
     auto *aa = reinterpret_cast<lks::AdjArgs<T> *>(c->arghost + (size_t)nfa * sizeof(lks::FwdArgs<T>));
@@ -708,12 +741,13 @@ int adjoint_impl(lks_ctx *c) {
         for (int seg = S - 1; seg >= 0; --seg) {
             const int n0 = seg * K + 1, n1 = std::min((seg + 1) * K, N);
             if (seg != S - 1) {
+                const int bank = bank_of(c, seg);
                 int cur = 0;
                 for (int n = n0; n <= n1; ++n) {
                     const int j = n - seg * K;
                     T *uin[3], *uout[3];
-                    traj_slot<T>(c, j - 1, uin);
-                    traj_slot<T>(c, j, uout);
+                    traj_slot<T>(c, bank, j - 1, uin);
+                    traj_slot<T>(c, bank, j, uout);
                     ra[n - 1] = make_fwd_args<T>(c, n, st[cur].r, uin, st[1 - cur].r, uout, rec_loc<T>(c, seg, n),
                                                  n < n1 ? rec_loc<T>(c, seg, n + 1) : nullptr, false);
                     cur = 1 - cur;
@@ -733,22 +767,34 @@ int adjoint_impl(lks_ctx *c) {
     const auto *dsa = reinterpret_cast<const lks::SensArgs<T> *>(reinterpret_cast<const char *>(daa) + (size_t)N * sizeof(lks::AdjArgs<T>));
     HIPCHK(c, lks::launch_fill<T>(ad.r, T(0), (long long)(1 + D) * L.F, c->stream));
     HIPCHK(c, lks::launch_fill<double>(c->G, 0.0, L.nd, c->stream));
+    hipStream_t sr = c->stream2 ? c->stream2 : c->stream;  // recompute stream
+    if (S > 1 && c->stream2) {  // stream2 starts after everything enqueued so far
+        HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
+        HIPCHK(c, hipStreamWaitEvent(c->stream2, c->ev_fork, 0));
+    }
     for (int seg = S - 1; seg >= 0; --seg) {
         const int n0 = seg * K + 1, n1 = std::min((seg + 1) * K, N);
-        if (seg != S - 1) {  // restore the checkpoint and recompute the segment
-            const T *ck = reinterpret_cast<const T *>(c->field(c->ckpt, (long long)seg * (1 + D)));
+        if (seg != S - 1 && sr != c->stream)  // segment seg was recomputed on stream2
+            HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_rec, 0));
+        if (seg >= 1) {  // restore and recompute segment seg - 1 into the other bank
+            const int ps = seg - 1, p0 = ps * K + 1, p1 = std::min((ps + 1) * K, N);
+            if (seg != S - 1 && sr != c->stream) HIPCHK(c, hipStreamWaitEvent(sr, c->ev_adj, 0));
+            const T *ck = reinterpret_cast<const T *>(c->field(c->ckpt, (long long)ps * (1 + D)));
             T *t0[3];
-            traj_slot<T>(c, 0, t0);
-            if ((rc = copy_fields<T>(c, st[0].r, ck, 1))) return rc;
-            if ((rc = copy_fields<T>(c, t0[0], ck + L.F, D))) return rc;
-            if ((rc = launch_xfer_dev<T>(c, dra + nrec + seg))) return rc;
-            for (int n = n0; n <= n1; ++n)
-                if ((rc = launch_fwd_dev<T>(c, dra + (n - 1), ra[n - 1].mode))) return rc;
+            traj_slot<T>(c, bank_of(c, ps), 0, t0);
+            if ((rc = copy_fields<T>(c, st[0].r, ck, 1, sr))) return rc;
+            if ((rc = copy_fields<T>(c, t0[0], ck + L.F, D, sr))) return rc;
+            if ((rc = launch_xfer_dev<T>(c, dra + nrec + ps, sr))) return rc;
+            for (int n = p0; n <= p1; ++n)
+                if ((rc = launch_fwd_dev<T>(c, dra + (n - 1), ra[n - 1].mode, sr))) return rc;
+            if (sr != c->stream) HIPCHK(c, hipEventRecord(c->ev_rec, sr));
         }
         for (int n = n1; n >= n0; --n)
             if ((rc = launch_adj_dev<T>(c, daa + (n - 1), dsa + (n - 1)))) return rc;
+        if (sr != c->stream) HIPCHK(c, hipEventRecord(c->ev_adj, c->stream));
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (sr != c->stream) HIPCHK(c, hipStreamSynchronize(sr));
     if ((rc = flush_timing(c))) return rc;
     c->have_adj = true;
     return LKS_OK;
@@ -805,9 +851,14 @@ int create_impl(const lks_desc *d, lks_ctx *c) {
     ALLOC(kprime, L.nd * 8)
     ALLOC(G, L.nd * 8)
     ALLOC(jn, (d->nsteps + 1) * 8)
-    ALLOC(partials, (d->objective.kind == LKS_OBJ_NONE ? 1 : (d->objective.n1 - d->objective.n0 + 1)) *
-                        L.max_blocks * 8)
+    ALLOC(partials, (size_t)L.prow * L.max_blocks * 8)
     ALLOC(counter, 64)
+    if (L.banks == 2) {  // recompute stream for the reverse sweep (default priority)
+        HIPCHK(c, hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking));
+        HIPCHK(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+        HIPCHK(c, hipEventCreateWithFlags(&c->ev_rec, hipEventDisableTiming));
+        HIPCHK(c, hipEventCreateWithFlags(&c->ev_adj, hipEventDisableTiming));
+    }
     c->flag = reinterpret_cast<int *>(reinterpret_cast<char *>(c->counter) + 32);
     HIPCHK(c, hipMemset(c->counter, 0, 64));
     HIPCHK(c, hipMemset(c->tile0, 0, 256));
@@ -889,6 +940,11 @@ struct RoundLists {
     std::vector<long long> atiles[3], ablk[3];
     std::vector<lks::SensArgs<T>> sens;
     std::vector<long long> sblk;
+    struct Reduce {
+        lks_ctx *c;
+        int na, nb;
+    };
+    std::vector<Reduce> red;  // objective rows to reduce after this round's forward launches
 };
 
 int list_of(const lks_ctx *c) { return c->d.dim == 2 ? 0 : (c->d.lattice == LKS_D3Q19 ? 1 : 2); }
@@ -951,14 +1007,14 @@ int plan_step(lks_ctx *c, RoundLists<T> &R, int *rc) {
             if ((*rc = copy_fields<T>(c, ck + L.F, st[cs.cur].u[0], D))) return 0;
             if (last) {
                 T *t0[3];
-                traj_slot<T>(c, 0, t0);
+                traj_slot<T>(c, 0, 0, t0);
                 if ((*rc = copy_fields<T>(c, t0[0], st[cs.cur].u[0], D))) return 0;
             }
         }
         T *uin[3], *uout[3];
         if (last) {
-            traj_slot<T>(c, j - 1, uin);
-            traj_slot<T>(c, j, uout);
+            traj_slot<T>(c, 0, j - 1, uin);
+            traj_slot<T>(c, 0, j, uout);
         } else {
             for (int k = 0; k < 3; ++k) {
                 uin[k] = st[cs.cur].u[k];
@@ -972,6 +1028,7 @@ int plan_step(lks_ctx *c, RoundLists<T> &R, int *rc) {
         R.fwd[li].push_back(make_fwd_args<T>(c, n, st[cs.cur].r, uin, st[1 - cs.cur].r, uout, fwd_loc<T>(c, n),
                                              n < N ? fwd_loc<T>(c, n + 1) : nullptr, true));
         R.ftiles[li].push_back(fwd_tiles(c, R.fwd[li].back().mode));
+        if (const int na = reduce_from(c, n)) R.red.push_back({c, na, n});
         cs.cur = 1 - cs.cur;
         cs.n = n + 1;
         return cs.n > N ? 1 : 0;
@@ -988,7 +1045,7 @@ int plan_step(lks_ctx *c, RoundLists<T> &R, int *rc) {
     if (cs.phase == PH_REC_BEGIN) {
         const T *ck = reinterpret_cast<const T *>(c->field(c->ckpt, (long long)cs.seg * (1 + D)));
         T *t0[3];
-        traj_slot<T>(c, 0, t0);
+        traj_slot<T>(c, bank_of(c, cs.seg), 0, t0);
         if ((*rc = copy_fields<T>(c, st[0].r, ck, 1))) return 0;
         if ((*rc = copy_fields<T>(c, t0[0], ck + L.F, D))) return 0;
         R.pre[li].push_back(make_xfer_args<T>(c, seg_lo(cs.seg), rec_loc<T>(c, cs.seg, seg_lo(cs.seg))));
@@ -1000,9 +1057,8 @@ int plan_step(lks_ctx *c, RoundLists<T> &R, int *rc) {
     if (cs.phase == PH_REC) {
         const int n = cs.n, j = n - cs.seg * K;
         T *uin[3], *uout[3];
-        traj_slot<T>(c, j - 1, uin);
-        traj_slot<T>(c, j, uout);
-        (void)j;
+        traj_slot<T>(c, bank_of(c, cs.seg), j - 1, uin);
+        traj_slot<T>(c, bank_of(c, cs.seg), j, uout);
         R.fwd[li].push_back(make_fwd_args<T>(c, n, st[cs.cur].r, uin, st[1 - cs.cur].r, uout,
                                              rec_loc<T>(c, cs.seg, n),
                                              n < seg_hi(cs.seg) ? rec_loc<T>(c, cs.seg, n + 1) : nullptr, false));
@@ -1039,11 +1095,9 @@ int end_forward(lks_ctx *c) {
     const Layout &L = c->L;
     const int D = c->d.dim, N = c->d.nsteps, K = L.K, S = L.S;
     Fields<T> st = state_fields<T>(c, c->field(c->state, (long long)c->cs.cur * (1 + D)));
-    HIPCHK(c, lks::launch_reduce_steps(c->partials, L.max_blocks, L.max_blocks, c->d.objective.n0,
-                                       c->d.objective.n1, c->obj_scale, c->jn, c->stream));
     Fields<T> fin = state_fields<T>(c, c->fin);
     T *ul[3];
-    traj_slot<T>(c, N - (S - 1) * K, ul);
+    traj_slot<T>(c, 0, N - (S - 1) * K, ul);
     int rc;
     if ((rc = copy_fields<T>(c, fin.r, st.r, 1))) return rc;
     if ((rc = copy_fields<T>(c, fin.u[0], ul[0], D))) return rc;
@@ -1173,6 +1227,14 @@ int round_impl(lks_batch *b, lks_ctx *const *cs, int n, int *done) {
             return LKS_EDEVICE;
         }
     }
+    for (const auto &r : R.red) {
+        hipError_t e = lks::launch_reduce_steps(r.c->partials, r.c->L.max_blocks, r.c->L.max_blocks, r.na, r.nb,
+                                                r.c->obj_scale, r.c->jn, b->stream);
+        if (e != hipSuccess) {
+            b->err = hipGetErrorString(e);
+            return LKS_EDEVICE;
+        }
+    }
     for (const Launch &L : ls) {  // sensitivity gathers after every adjoint step of the round
         if (L.kind != 2) continue;
         hipError_t e = lks::launch_sens_batch<T>(reinterpret_cast<const lks::SensArgs<T> *>(dv + L.args),
@@ -1257,6 +1319,12 @@ int lks_create(const lks_desc *d, lks_ctx **out) {
 void lks_destroy(lks_ctx *c) {
     if (!c) return;
     if (c->stream || !c->allocs.empty()) (void)hipStreamSynchronize(c->stream);
+    if (c->stream2) {
+        (void)hipStreamSynchronize(c->stream2);
+        (void)hipStreamDestroy(c->stream2);
+    }
+    for (hipEvent_t e : {c->ev_fork, c->ev_rec, c->ev_adj})
+        if (e) (void)hipEventDestroy(e);
     for (void *p : c->allocs) (void)hipFree(p);
     for (auto &ev : c->pool) {
         if (ev.a) (void)hipEventDestroy(ev.a);

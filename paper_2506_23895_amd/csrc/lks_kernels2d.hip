@@ -84,32 +84,31 @@ __device__ __noinline__ double fwd2d_push(const FwdArgs<T> &a, int c, int o, T r
     return j;
 }
 
-template <typename T>
-__device__ __forceinline__ void fwd2d_body(const FwdArgs<T> &a, int bx, int by, long long slot0) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+__device__ __forceinline__ float rcp_t(float v) { return __builtin_amdgcn_rcpf(v); }
+__device__ __forceinline__ double rcp_t(double v) { return 1.0 / v; }
+
+// IN: the wave touches no face, needs no periodic wrap and every E row it evaluates has central
+// differences on both axes (decided per wave), so the bounds, wrap, one-sided and boundary-push
+// code is compiled out.
+template <typename T, bool IN>
+__device__ __forceinline__ void fwd2d_rows(const FwdArgs<T> &a, int strip, int y0, long long pslot,
+                                           bool obj_on) {
+    const int lane = threadIdx.x & 63;
     const Geom &g = a.g;
     const int nx = g.n[0], ny = g.n[1];
-    const int strip = bx * WPB + w;
-    const long long pslot = slot0 + w;
-    const bool obj_on = a.obj.active && a.obj.kind != OBJ_NONE;
-    const int nstrips = (nx + SW - 1) / SW;
-    if (strip >= nstrips) {
-        if (obj_on && lane == 0) a.obj.partials[pslot] = 0.0;
-        return;
-    }
     const int c = strip * SW - 2 + lane;
     int cw = c;
-    const bool cin = wrapc(cw, nx, g.per[0]);
+    const bool cin = IN || wrapc(cw, nx, g.per[0]);
     const int cmin = strip * SW - 2, cmax = cmin + 63;
-    const bool xface = !g.per[0] && ((cmin <= 0 && 0 <= cmax) || (cmin <= nx - 1 && nx - 1 <= cmax));
-    const bool out_lane = lane >= 2 && lane < 62 && c < nx && !on_face(g, 0, c);
-    const int y0 = by * RY;
+    const bool xface = !IN && !g.per[0] && ((cmin <= 0 && 0 <= cmax) || (cmin <= nx - 1 && nx - 1 <= cmax));
+    const bool out_lane = lane >= 2 && lane < 62 && (IN || (c < nx && !on_face(g, 0, c)));
     const T *__restrict__ ux_in = a.uin[0];
     const T *__restrict__ uy_in = a.uin[1];
     const T *__restrict__ r_in = a.rin;
     // does this wave's rectangle meet the footprint box (wave-uniform)?
     const bool wbox = a.m.hi[0] >= strip * SW && a.m.lo[0] < strip * SW + SW && a.m.hi[1] >= y0 &&
                       a.m.lo[1] < y0 + RY;
+    const bool brink = wbox || a.kstatic != nullptr;  // kappa + kappa_s can be non-zero here
 
     // every row this wave needs, requested before any arithmetic
     T ux[RY + 5], uy[RY + 5], rv[RY + 2];
@@ -129,7 +128,12 @@ __device__ __forceinline__ void fwd2d_body(const FwdArgs<T> &a, int bx, int by, 
     for (int k = 0; k < RY + 5; ++k) {
         int yw = y0 - 3 + k;
         ux[k] = uy[k] = T(0);
-        if (cin && wrapc(yw, ny, g.per[1])) {
+        if (IN) {
+            if (k == 0) continue;  // the one-sided stencils that read row y0 - 3 never run here
+            const long long idx = c + (long long)yw * g.sy;
+            ux[k] = ux_in[idx];
+            uy[k] = uy_in[idx];
+        } else if (cin && wrapc(yw, ny, g.per[1])) {
             const long long idx = cw + yw * g.sy;
             ux[k] = ux_in[idx];
             uy[k] = uy_in[idx];
@@ -139,59 +143,62 @@ __device__ __forceinline__ void fwd2d_body(const FwdArgs<T> &a, int bx, int by, 
     for (int k = 0; k < RY + 2; ++k) {
         int yw = y0 - 1 + k;
         rv[k] = T(0);
-        if (cin && wrapc(yw, ny, g.per[1])) rv[k] = r_in[cw + yw * g.sy];
+        if (IN) rv[k] = r_in[c + (long long)yw * g.sy];
+        else if (cin && wrapc(yw, ny, g.per[1])) rv[k] = r_in[cw + yw * g.sy];
     }
 
     T acc_r[3] = {0, 0, 0}, acc_m[3] = {0, 0, 0};  // own column: rho*, m_y* for rows r-1, r, r+1
     T trr[3] = {0, 0, 0}, trm[3] = {0, 0, 0};      // pulled by column c+1
     T tlr[3] = {0, 0, 0}, tlm[3] = {0, 0, 0};      // pulled by column c-1
     double jacc = 0.0;
-    const T A2 = T(2) * a.A;
+    const T A = a.A;
     const T wa = T(d2q9::WA), wd = T(d2q9::WD), w0 = T(d2q9::W0);
 
 #pragma unroll
     for (int e = 0; e < RY + 2; ++e) {
         const int r = y0 - 1 + e;  // row of the E_i evaluated now; u rows r-2..r+2 = ux[e..e+4]
         int rw = r;
-        if (wrapc(rw, ny, g.per[1])) {  // wave-uniform
+        if (IN || wrapc(rw, ny, g.per[1])) {  // wave-uniform
             const T uxc = ux[e + 2], uyc = uy[e + 2];
             const T uxl = from_left(uxc), uxr = from_right(uxc);
             const T uyl = from_left(uyc), uyr = from_right(uyc);
-            T dxux = T(0.5) * (uxr - uxl), dxuy = T(0.5) * (uyr - uyl);
-            if (xface) {
+            // twice the derivatives: central (f+ - f-), one-sided 2 (-1.5 f0 + 2 f1 - 0.5 f2)
+            T gxux = uxr - uxl, gxuy = uyr - uyl;
+            if (!IN && xface) {
                 const T uxll = from_left(uxl), uxrr = from_right(uxr);
                 const T uyll = from_left(uyl), uyrr = from_right(uyr);
                 if (c == 0) {
-                    dxux = T(-1.5) * uxc + T(2) * uxr - T(0.5) * uxrr;
-                    dxuy = T(-1.5) * uyc + T(2) * uyr - T(0.5) * uyrr;
+                    gxux = T(-3) * uxc + T(4) * uxr - uxrr;
+                    gxuy = T(-3) * uyc + T(4) * uyr - uyrr;
                 } else if (c == nx - 1) {
-                    dxux = T(1.5) * uxc - T(2) * uxl + T(0.5) * uxll;
-                    dxuy = T(1.5) * uyc - T(2) * uyl + T(0.5) * uyll;
+                    gxux = T(3) * uxc - T(4) * uxl + uxll;
+                    gxuy = T(3) * uyc - T(4) * uyl + uyll;
                 }
             }
-            T dyux, dyuy;
-            if (!g.per[1] && rw == 0) {
-                dyux = T(-1.5) * uxc + T(2) * ux[e + 3] - T(0.5) * ux[e + 4];
-                dyuy = T(-1.5) * uyc + T(2) * uy[e + 3] - T(0.5) * uy[e + 4];
-            } else if (!g.per[1] && rw == ny - 1) {
-                dyux = T(1.5) * uxc - T(2) * ux[e + 1] + T(0.5) * ux[e];
-                dyuy = T(1.5) * uyc - T(2) * uy[e + 1] + T(0.5) * uy[e];
-            } else {
-                dyux = T(0.5) * (ux[e + 3] - ux[e + 1]);
-                dyuy = T(0.5) * (uy[e + 3] - uy[e + 1]);
+            T gyux = ux[e + 3] - ux[e + 1], gyuy = uy[e + 3] - uy[e + 1];
+            if (!IN && !g.per[1] && rw == 0) {
+                gyux = T(-3) * uxc + T(4) * ux[e + 3] - ux[e + 4];
+                gyuy = T(-3) * uyc + T(4) * uy[e + 3] - uy[e + 4];
+            } else if (!IN && !g.per[1] && rw == ny - 1) {
+                gyux = T(3) * uxc - T(4) * ux[e + 1] + ux[e];
+                gyuy = T(3) * uyc - T(4) * uy[e + 1] + uy[e];
             }
             const T a0 = rv[e] - T(1.5) * (uxc * uxc + uyc * uyc);
             const T bx3 = T(3) * uxc, by3 = T(3) * uyc;
-            const T txx = T(4.5) * uxc * uxc + A2 * dxux;
-            const T tyy = T(4.5) * uyc * uyc + A2 * dyuy;
-            const T txy2 = T(9) * uxc * uyc + A2 * (dyux + dxuy);
+            const T txx = T(4.5) * uxc * uxc + A * gxux;
+            const T tyy = T(4.5) * uyc * uyc + A * gyuy;
+            const T txy2 = T(9) * uxc * uyc + A * (gyux + gxuy);
             const T q = a0 + txx + tyy;
-            const T m = cin ? T(1) : T(0);  // nothing from columns outside the domain
-            const T e0 = m * w0 * a0;
-            const T e1 = m * wa * (a0 + bx3 + txx), e3 = m * wa * (a0 - bx3 + txx);
-            const T e2 = m * wa * (a0 + by3 + tyy), e4 = m * wa * (a0 - by3 + tyy);
-            const T e5 = m * wd * (q + bx3 + by3 + txy2), e6 = m * wd * (q - bx3 + by3 - txy2);
-            const T e7 = m * wd * (q - bx3 - by3 + txy2), e8 = m * wd * (q + bx3 - by3 - txy2);
+            const T m = (IN || cin) ? T(1) : T(0);  // nothing from columns outside the domain
+            T e0 = w0 * a0;
+            T e1 = wa * (a0 + bx3 + txx), e3 = wa * (a0 - bx3 + txx);
+            T e2 = wa * (a0 + by3 + tyy), e4 = wa * (a0 - by3 + tyy);
+            T e5 = wd * (q + bx3 + by3 + txy2), e6 = wd * (q - bx3 + by3 - txy2);
+            T e7 = wd * (q - bx3 - by3 + txy2), e8 = wd * (q + bx3 - by3 - txy2);
+            if (!IN) {
+                e0 *= m; e1 *= m; e2 *= m; e3 *= m; e4 *= m;
+                e5 *= m; e6 *= m; e7 *= m; e8 *= m;
+            }
             acc_r[1] += e0;
             acc_r[2] += e2;
             acc_m[2] += e2;
@@ -212,15 +219,18 @@ __device__ __forceinline__ void fwd2d_body(const FwdArgs<T> &a, int bx, int by, 
             const int o = r - 1;
             const T fr = from_left(trr[0]), fm = from_left(trm[0]);
             const T gr = from_right(tlr[0]), gm = from_right(tlm[0]);
-            if (out_lane && o < ny && !on_face(g, 1, o)) {
+            if (out_lane && (IN || (o < ny && !on_face(g, 1, o)))) {
                 const T rs = acc_r[0] + fr + gr, mx = fr - gr, my = acc_m[0] + fm + gm;
                 const T kap = kb[e - 2];
                 const T us0 = sbx[e - 2], us1 = sby[e - 2];
-                const long long idx = c + o * g.sy;
-                const T ks = a.kstatic ? a.kstatic[idx] : T(0);
-                const T inv = T(1) / (T(1) + kap + ks);
-                const T nux = (mx + kap * us0 + a.gf[0]) * inv;
-                const T nuy = (my + kap * us1 + a.gf[1]) * inv;
+                const long long idx = c + (long long)o * g.sy;
+                T nux = mx + a.gf[0], nuy = my + a.gf[1];
+                if (brink) {
+                    const T ks = a.kstatic ? a.kstatic[idx] : T(0);
+                    const T inv = rcp_t(T(1) + kap + ks);
+                    nux = (nux + kap * us0) * inv;
+                    nuy = (nuy + kap * us1) * inv;
+                }
                 a.rout[idx] = rs;
                 a.uout[0][idx] = nux;
                 a.uout[1][idx] = nuy;
@@ -228,7 +238,7 @@ __device__ __forceinline__ void fwd2d_body(const FwdArgs<T> &a, int bx, int by, 
                     const T uv[3] = {nux, nuy, T(0)}, usv[3] = {us0, us1, T(0)};
                     jacc += obj_density<T>(a.obj, c, o, 0, (double)rs, uv, kap, usv);
                 }
-                if (c == 1 || c == nx - 2 || o == 1 || o == ny - 2)
+                if (!IN && (c == 1 || c == nx - 2 || o == 1 || o == ny - 2))
                     jacc += fwd2d_push<T>(a, c, o, rs, nux, nuy, obj_on);
             }
         }
@@ -246,11 +256,41 @@ __device__ __forceinline__ void fwd2d_body(const FwdArgs<T> &a, int bx, int by, 
     }
 }
 
+template <typename T>
+__device__ __forceinline__ void fwd2d_body(const FwdArgs<T> &a, int bx, int by, long long slot0) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const Geom &g = a.g;
+    const int nx = g.n[0], ny = g.n[1];
+    const int strip = bx * WPB + w;
+    const long long pslot = slot0 + w;
+    const bool obj_on = a.obj.active && a.obj.kind != OBJ_NONE;
+    const int nstrips = (nx + SW - 1) / SW;
+    if (strip >= nstrips) {
+        if (obj_on && lane == 0) a.obj.partials[pslot] = 0.0;
+        return;
+    }
+    const int y0 = by * RY, cmin = strip * SW - 2;
+    if (cmin >= 0 && cmin + 63 <= nx - 1 && y0 >= 2 && y0 + RY <= ny - 2)
+        fwd2d_rows<T, true>(a, strip, y0, pslot, obj_on);
+    else
+        fwd2d_rows<T, false>(a, strip, y0, pslot, obj_on);
+}
+
 __host__ __device__ inline int fwd2d_grid_x(const Geom &g) {
     const int nstrips = (g.n[0] + SW - 1) / SW;
     return (nstrips + WPB - 1) / WPB;
 }
 __host__ __device__ inline int fwd2d_grid_y(const Geom &g) { return (g.n[1] + RY - 1) / RY; }
+
+#ifndef LKS_TILE_ENDS_FIRST
+#define LKS_TILE_ENDS_FIRST 1
+#endif
+// row chunk of the r-th dispatched chunk row: alternately from both ends, so the waves that touch
+// the y faces (the slower general path) start early instead of forming the tail of the launch
+__device__ __forceinline__ int chunk_row(int r, int gy) {
+    if (!LKS_TILE_ENDS_FIRST) return r;
+    return (r & 1) ? gy - 1 - (r >> 1) : (r >> 1);
+}
 
 // first tile of the job that owns flat tile b (tile0 ascending, tile0[0] = 0)
 __device__ __forceinline__ int job_of(const long long *tile0, int njobs, long long b) {
@@ -269,21 +309,22 @@ __global__ __launch_bounds__(kBlock) void k_fwd2d_batch(const FwdArgs<T> *args, 
     const long long b = blockIdx.x;
     const int j = job_of(tile0, njobs, b);
     const FwdArgs<T> &a = args[j];
-    const long long t = b - tile0[j];
+    const long long t = njobs == 1 ? b : b - tile0[j];  // one job: tile0 = {0}
     const long long ns = (a.mode & FWD_STENCIL) ? (long long)fwd2d_grid_x(a.g) * fwd2d_grid_y(a.g) : 0;
     if (t >= ns) {  // extra blocks: transfer of the next step onto its footprint box
         transfer_box<T, 2, kBlock>(a.des, a.mnext, a.box, a.knext, a.usnext, t - ns);
         return;
     }
     const int nbx = fwd2d_grid_x(a.g);
-    fwd2d_body<T>(a, (int)(t % nbx), (int)(t / nbx), t * WPB);
+    fwd2d_body<T>(a, (int)(t % nbx), chunk_row((int)(t / nbx), fwd2d_grid_y(a.g)), t * WPB);
 }
 
 // transposed difference operator along one axis at coordinate c: sum_r D[r][c] f(r), with f
 // given for r = c-2 .. c+2 (rows off the grid are never read)
 template <typename T>
 __device__ __forceinline__ T deriv_T(const T f[5], int c, int n, int per) {
-    if (per) return T(0.5) * (f[1] - f[3]);
+    // rows c-2 .. c+2 all use central differences: only D[c-1][c] = 1/2 and D[c+1][c] = -1/2
+    if (per || (c >= 3 && c <= n - 4)) return T(0.5) * (f[1] - f[3]);
     T acc = 0;
 #pragma unroll
     for (int o = -2; o <= 2; ++o) {
@@ -298,158 +339,247 @@ __device__ __forceinline__ T deriv_T(const T f[5], int c, int n, int per) {
     return acc;
 }
 
-template <typename T>
-__device__ __forceinline__ void adj2d_body(const AdjArgs<T> &a, int bx, int by) {
-    constexpr int LX = TX + 8, LY = TY + 8;  // lambda, halo 4, origin (x0-4, y0-4)
-    constexpr int PX = TX + 6, PY = TY + 6;  // P*, V*, halo 3, origin (x0-3, y0-3)
-    constexpr int MX = TX + 4, MY = TY + 4;  // moments, halo 2, origin (x0-2, y0-2)
-    constexpr int NBUF = (3 * LX * LY > 6 * MX * MY) ? 3 * LX * LY : 6 * MX * MY;
-    __shared__ T sbuf[NBUF];  // lambda, then the moments
-    __shared__ T sPV[3][PY][PX];
+// Adjoint step as wave strips marching along y, the transpose of the forward step taken in
+// reverse order.  Lane l of a wave holds column c = 58 * strip - 3 + l; lanes 3..60 produce
+// outputs.  Per row of the wave's window:
+//   lambda = Lambda^n + dj^n/dX^n                        (loaded rows, objective added)
+//   (P*, V*) = boundary transpose of lambda, V* / (1 + kappa + kappa_s), zero on face nodes;
+//   kappa_bar = -V*.(u^n - u_S) + dj/dkappa on the wave's own footprint nodes
+//   moments of E~_i(y) = P*(y + c_i) + c_i.V*(y + c_i) with weights w_i c_i^a c_i^b: the D2Q9
+//   weights factor as w(c_x) w(c_y) (2/3 for 0, 1/6 for +-1), so each moment is a 1D x-stencil
+//   of P*, V* (lane shifts) followed by a 1D y-stencil (rows held in registers)
+//   Lambda^{n-1} = (rho~, 3 u~ + 9 s~.u - 3 rho~ u + 2A sum_b D_b^T s~_ab)
+// Every lane that a needed P* sits on has both neighbours inside the wave, so the boundary
+// seeds of column-adjacent faces come from lane shifts as well.
+constexpr int SWA = 58;  // output columns per adjoint wave strip
+constexpr int RYA = 4;   // output rows per wave
+constexpr int RGA = 2;   // rows per pass in waves that touch a face or wrap
 
-    const int tid = threadIdx.x;
-    const int x0 = bx * TX, y0 = by * TY;
+__host__ __device__ inline int adj2d_grid_x(const Geom &g) {
+    const int nstrips = (g.n[0] + SWA - 1) / SWA;
+    return (nstrips + WPB - 1) / WPB;
+}
+__host__ __device__ inline int adj2d_grid_y(const Geom &g) { return (g.n[1] + RYA - 1) / RYA; }
+
+template <typename T, bool IN, int NR>
+__device__ __forceinline__ void adj2d_rows(const AdjArgs<T> &a, int strip, int y0) {
+    constexpr int H = IN ? 1 : 2;          // moment rows beyond the outputs (strain transpose)
+    constexpr int NM = NR + 2 * H;         // moment rows y0 - H ..
+    constexpr int NP = NM + 2;             // P*, V* rows y0 - H - 1 ..
+    constexpr int NL = IN ? NP : NP + 2;   // lambda rows (one more each side for boundary seeds)
+    constexpr int LOFF = IN ? 0 : 1;       // lambda row of P* row 0
+    const int lane = threadIdx.x & 63;
     const Geom &g = a.g;
     const int nx = g.n[0], ny = g.n[1];
+    const int c = strip * SWA - 3 + lane;
+    int cw = c;
+    const bool cin = IN || wrapc(cw, nx, g.per[0]);
+    const int yp0 = y0 - H - 1, yl0 = yp0 - LOFF;
     const bool obj_on = a.obj.active && a.obj.kind != OBJ_NONE;
     const bool kobj = obj_on && obj_uses_kappa(a.obj.kind);
     const double sc = a.obj.scale;
-    T(*sl)[LY][LX] = reinterpret_cast<T(*)[LY][LX]>(sbuf);
+    const int cmin = strip * SWA - 3;
+    const bool wbox = a.m.hi[0] >= cmin && a.m.lo[0] <= cmin + 63 && a.m.hi[1] >= yl0 &&
+                      a.m.lo[1] <= yl0 + NL - 1;
+    const bool brink = wbox || a.kstatic != nullptr;
 
-    // lambda = Lambda^n + dj^n/dX^n on halo 4
-    for (int i = tid; i < LX * LY; i += kBlock) {
-        const int lx = i % LX, ly = i / LX;
-        int gx = x0 - 4 + lx, gy = y0 - 4 + ly;
-        T P = 0, Vx = 0, Vy = 0;
-        if (wrapc(gx, nx, g.per[0]) && wrapc(gy, ny, g.per[1])) {
-            const long long idx = gx + gy * g.sy;
-            P = a.Pin[idx];
-            Vx = a.Vin[0][idx];
-            Vy = a.Vin[1][idx];
-            if (obj_on && (!a.obj.mask || a.obj.mask[idx])) {
-                double kap = 0.0, us[3] = {0, 0, 0};
-                if (kobj && in_box(a.m, 2, gx, gy, 0)) {
-                    const long long bi = box_index(a.box, a.m, 2, gx, gy, 0);
-                    kap = a.kbox[bi];
-                    us[0] = a.usbox[0][bi];
-                    us[1] = a.usbox[1][bi];
-                }
-                double dP, dV[3];
-                obj_dstate(a.obj, gx, gy, 0, kap, us, dP, dV);
-                P += (T)(sc * dP);
-                Vx += (T)(sc * dV[0]);
-                Vy += (T)(sc * dV[1]);
-            }
-        }
-        sl[0][ly][lx] = P;
-        sl[1][ly][lx] = Vx;
-        sl[2][ly][lx] = Vy;
-    }
-    __syncthreads();
-
-    // boundary transpose + force transpose on halo 3; kappa_bar on the tile's own nodes
-    for (int i = tid; i < PX * PY; i += kBlock) {
-        const int lx = i % PX, ly = i / PX;
-        const int gxu = x0 - 3 + lx, gyu = y0 - 3 + ly;  // unwrapped
-        int gx = gxu, gy = gyu;
-        T P = 0, Vx = 0, Vy = 0;
-        if (wrapc(gx, nx, g.per[0]) && wrapc(gy, ny, g.per[1]) && !on_face(g, 0, gx) &&
-            !on_face(g, 1, gy)) {
-            const int llx = lx + 1, lly = ly + 1;  // position in sl
-            T acc[4] = {sl[0][lly][llx], sl[1][lly][llx], sl[2][lly][llx], T(0)};
-            const int c[3] = {gx, gy, 0};
-            gather_boundary_T<2>(g, a.bc.kind, c, acc, [&](const int p[3], int comp) -> T {
-                return sl[comp][lly + (p[1] - gy)][llx + (p[0] - gx)];
-            });
-            const long long idx = gx + gy * g.sy;
-            T kap = 0, us[3] = {0, 0, 0};
-            const bool inb = in_box(a.m, 2, gx, gy, 0);
-            long long bi = 0;
-            if (inb) {
-                bi = box_index(a.box, a.m, 2, gx, gy, 0);
-                kap = a.kbox[bi];
-                us[0] = a.usbox[0][bi];
-                us[1] = a.usbox[1][bi];
-            }
-            const T ks = a.kstatic ? a.kstatic[idx] : T(0);
-            const T inv = T(1) / (T(1) + kap + ks);
-            P = acc[0];
-            Vx = acc[1] * inv;
-            Vy = acc[2] * inv;
-            const bool own = lx >= 3 && lx < 3 + TX && ly >= 3 && ly < 3 + TY && gxu < nx && gyu < ny;
-            if (own && inb) {
-                const T ux = a.ucur[0][idx], uy = a.ucur[1][idx];
-                double kb = -((double)Vx * ((double)ux - (double)us[0]) +
-                              (double)Vy * ((double)uy - (double)us[1]));
-                if (kobj && (!a.obj.mask || a.obj.mask[idx])) {
-                    const double uu[3] = {(double)ux, (double)uy, 0.0};
-                    const double uss[3] = {(double)us[0], (double)us[1], 0.0};
-                    kb += sc * obj_dkappa(a.obj, gx, gy, 0, uu, uss);
-                }
-                a.kbar[bi] = (T)kb;
-            }
-        }
-        sPV[0][ly][lx] = P;
-        sPV[1][ly][lx] = Vx;
-        sPV[2][ly][lx] = Vy;
-    }
-    __syncthreads();
-
-    // pull transpose and the w-weighted moments (the paper's Eqs. arho, au, as) on halo 2
-    T(*sm)[MY][MX] = reinterpret_cast<T(*)[MY][MX]>(sbuf);
-    for (int i = tid; i < MX * MY; i += kBlock) {
-        const int lx = i % MX, ly = i / MX;
-        const int px = lx + 1, py = ly + 1;  // position in sPV
-        T rt = 0, utx = 0, uty = 0, sxx = 0, sxy = 0, syy = 0;
+    // ---- lambda rows (and kappa, u_S where the footprint box meets the wave) ----
+    T lp[NL], lx[NL], ly[NL], kk[NL], ksx[NL], ksy[NL];
+    bool lv[NL];
 #pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            const int cx = d2q9::cx(q), cy = d2q9::cy(q);
-            const T eb = sPV[0][py + cy][px + cx] + T(cx) * sPV[1][py + cy][px + cx] +
-                         T(cy) * sPV[2][py + cy][px + cx];
-            const T we = T(d2q9::wt(q)) * eb;
-            rt += we;
-            utx += T(cx) * we;
-            uty += T(cy) * we;
-            sxx += T(cx * cx) * we;
-            sxy += T(cx * cy) * we;
-            syy += T(cy * cy) * we;
+    for (int k = 0; k < NL; ++k) {
+        int rw = yl0 + k;
+        lv[k] = cin && (IN || wrapc(rw, ny, g.per[1]));
+        lp[k] = lx[k] = ly[k] = kk[k] = ksx[k] = ksy[k] = T(0);
+        if (!lv[k]) continue;
+        const long long idx = cw + (long long)rw * g.sy;
+        lp[k] = a.Pin[idx];
+        lx[k] = a.Vin[0][idx];
+        ly[k] = a.Vin[1][idx];
+        if (wbox && in_box(a.m, 2, cw, rw, 0)) {
+            const long long bi = box_index(a.box, a.m, 2, cw, rw, 0);
+            kk[k] = a.kbox[bi];
+            ksx[k] = a.usbox[0][bi];
+            ksy[k] = a.usbox[1][bi];
         }
-        sm[0][ly][lx] = rt;
-        sm[1][ly][lx] = utx;
-        sm[2][ly][lx] = uty;
-        sm[3][ly][lx] = sxx;
-        sm[4][ly][lx] = sxy;
-        sm[5][ly][lx] = syy;
     }
-    __syncthreads();
+    // velocities the outputs and kappa_bar need, requested with the lambda rows
+    const bool out_lane = lane >= 3 && lane <= 60 && c < nx;
+    T upx[NR], upy[NR], ucx[NR], ucy[NR];
+#pragma unroll
+    for (int ko = 0; ko < NR; ++ko) {
+        const int o = y0 + ko;
+        upx[ko] = upy[ko] = ucx[ko] = ucy[ko] = T(0);
+        if (!out_lane || o >= ny) continue;
+        const long long idx = c + (long long)o * g.sy;
+        upx[ko] = a.uprev[0][idx];
+        upy[ko] = a.uprev[1][idx];
+        if (wbox && in_box(a.m, 2, c, o, 0)) {
+            ucx[ko] = a.ucur[0][idx];
+            ucy[ko] = a.ucur[1][idx];
+        }
+    }
+    if (obj_on) {
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            int rw = yl0 + k;
+            if (!lv[k]) continue;
+            if (!IN) wrapc(rw, ny, g.per[1]);
+            const long long idx = cw + (long long)rw * g.sy;
+            if (a.obj.mask && !a.obj.mask[idx]) continue;
+            if (kobj && kk[k] == T(0)) continue;  // kappa objectives vanish off the body
+            const double us[3] = {(double)ksx[k], (double)ksy[k], 0.0};
+            double dP, dV[3];
+            obj_dstate(a.obj, cw, rw, 0, (double)kk[k], us, dP, dV);
+            lp[k] += (T)(sc * dP);
+            lx[k] += (T)(sc * dV[0]);
+            ly[k] += (T)(sc * dV[1]);
+        }
+    }
 
-    // transposed equilibrium and strain: Lambda^{n-1}
+    // ---- (P*, V*): boundary transpose and force transpose; kappa_bar on own nodes ----
+    T pp[NP], px[NP], py[NP];
+    const bool xadj = !IN && !g.per[0] && (cmin <= 1 || cmin + 63 >= nx - 2);  // seeds via lane shifts
+#pragma unroll
+    for (int kp = 0; kp < NP; ++kp) {
+        const int k = kp + LOFF;
+        int rw = yp0 + kp;
+        T P = lp[k], Vx = lx[k], Vy = ly[k];
+        if (!IN) {
+            // shifted lambda of rows k-1..k+1 (every lane runs the shifts)
+            T sL[3][3], sR[3][3];
+            if (xadj) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const int kd = k - 1 + d;
+                    sL[d][0] = from_left(lp[kd]); sR[d][0] = from_right(lp[kd]);
+                    sL[d][1] = from_left(lx[kd]); sR[d][1] = from_right(lx[kd]);
+                    sL[d][2] = from_left(ly[kd]); sR[d][2] = from_right(ly[kd]);
+                }
+            }
+            const bool rin = wrapc(rw, ny, g.per[1]);
+            if (lv[k] && rin && !on_face(g, 0, cw) && !on_face(g, 1, rw)) {
+                T acc[4] = {P, Vx, Vy, T(0)};
+                const int c3[3] = {cw, rw, 0};
+                gather_boundary_T<2>(g, a.bc.kind, c3, acc, [&](const int p[3], int comp) -> T {
+                    const int dy = p[1] - rw, dx = p[0] - cw;
+                    T v0, vm, vp;  // rows k-1, k, k+1 at column p[0]
+                    if (dx == 0) {
+                        v0 = comp == 0 ? lp[k] : comp == 1 ? lx[k] : ly[k];
+                        vm = comp == 0 ? lp[k - 1] : comp == 1 ? lx[k - 1] : ly[k - 1];
+                        vp = comp == 0 ? lp[k + 1] : comp == 1 ? lx[k + 1] : ly[k + 1];
+                    } else {
+                        const T(*sh)[3] = dx < 0 ? sL : sR;
+                        v0 = sh[1][comp];
+                        vm = sh[0][comp];
+                        vp = sh[2][comp];
+                    }
+                    return dy == 0 ? v0 : dy < 0 ? vm : vp;
+                });
+                P = acc[0];
+                Vx = acc[1];
+                Vy = acc[2];
+            } else {
+                P = Vx = Vy = T(0);
+            }
+        }
+        if (brink) {  // rw is wrapped here whenever lv[k] holds
+            const T ks = (a.kstatic && lv[k]) ? a.kstatic[cw + (long long)rw * g.sy] : T(0);
+            const T inv = rcp_t(T(1) + kk[k] + ks);
+            Vx *= inv;
+            Vy *= inv;
+        }
+        pp[kp] = P;
+        px[kp] = Vx;
+        py[kp] = Vy;
+        // kappa_bar on the wave's own nodes of the footprint box
+        const int o = yp0 + kp;
+        if (wbox && kp >= H + 1 && kp < H + 1 + NR && out_lane && o < ny && in_box(a.m, 2, c, o, 0)) {
+            const long long idx = c + (long long)o * g.sy;
+            const long long bi = box_index(a.box, a.m, 2, c, o, 0);
+            const T ux = ucx[kp - H - 1], uy = ucy[kp - H - 1];
+            double kb = -((double)Vx * ((double)ux - (double)ksx[k]) + (double)Vy * ((double)uy - (double)ksy[k]));
+            if (kobj && (!a.obj.mask || a.obj.mask[idx])) {
+                const double uu[3] = {(double)ux, (double)uy, 0.0};
+                const double uss[3] = {(double)ksx[k], (double)ksy[k], 0.0};
+                kb += sc * obj_dkappa(a.obj, c, o, 0, uu, uss);
+            }
+            a.kbar[bi] = (T)kb;
+        }
+    }
+
+    // ---- x-stencils of each P* row: a0 = M0 P + M1 Vx, a1 = M1 P + M2 Vx, a2 = M2 P + M1 Vx,
+    //      b_j = M_j Vy, with M0 f = 2/3 f + 1/6 (f+ + f-), M1 f = 1/6 (f+ - f-), M2 f = 1/6 (f+ + f-)
+    const T s6 = T(1) / T(6), t3 = T(2) / T(3);
+    T xa0[NP], xa1[NP], xa2[NP], xb0[NP], xb1[NP], xb2[NP];
+#pragma unroll
+    for (int kp = 0; kp < NP; ++kp) {
+        const T pl = from_left(pp[kp]), pr = from_right(pp[kp]);
+        const T vxl = from_left(px[kp]), vxr = from_right(px[kp]);
+        const T vyl = from_left(py[kp]), vyr = from_right(py[kp]);
+        const T m0p = t3 * pp[kp] + s6 * (pr + pl), m1p = s6 * (pr - pl), m2p = s6 * (pr + pl);
+        const T m1x = s6 * (vxr - vxl), m2x = s6 * (vxr + vxl);
+        xa0[kp] = m0p + m1x;
+        xa1[kp] = m1p + m2x;
+        xa2[kp] = m2p + m1x;
+        xb0[kp] = t3 * py[kp] + s6 * (vyr + vyl);
+        xb1[kp] = s6 * (vyr - vyl);
+        xb2[kp] = s6 * (vyr + vyl);
+    }
+    // ---- y-stencils: moment rows (P* rows km, km + 1, km + 2 = y - 1, y, y + 1) ----
+    T mr[NM], mux[NM], muy[NM], mxx[NM], mxy[NM], myy[NM];
+#pragma unroll
+    for (int km = 0; km < NM; ++km) {
+        const int j = km + 1;
+        const T sa0 = xa0[j + 1] + xa0[j - 1], da0 = xa0[j + 1] - xa0[j - 1];
+        const T sa1 = xa1[j + 1] + xa1[j - 1], da1 = xa1[j + 1] - xa1[j - 1];
+        const T sa2 = xa2[j + 1] + xa2[j - 1];
+        const T sb0 = xb0[j + 1] + xb0[j - 1], db0 = xb0[j + 1] - xb0[j - 1];
+        const T sb1 = xb1[j + 1] + xb1[j - 1], db1 = xb1[j + 1] - xb1[j - 1];
+        const T db2 = xb2[j + 1] - xb2[j - 1];
+        myy[km] = s6 * (sa0 + db0);
+        mr[km] = t3 * xa0[j] + myy[km];
+        mux[km] = t3 * xa1[j] + s6 * (sa1 + db1);
+        mxx[km] = t3 * xa2[j] + s6 * (sa2 + db2);
+        muy[km] = s6 * (da0 + sb0);
+        mxy[km] = s6 * (da1 + sb1);
+    }
+
+    // ---- Lambda^{n-1} on the output rows ----
     const T A2 = T(2) * a.A;
-    for (int k = 0; k < (TX * TY) / kBlock; ++k) {
-        const int lx = tid % TX, ly = tid / TX + k * (kBlock / TX);
-        const int gx = x0 + lx, gy = y0 + ly;
-        if (gx >= nx || gy >= ny) continue;
-        const long long idx = gx + gy * g.sy;
-        const int mx = lx + 2, my = ly + 2;
-        const T rt = sm[0][my][mx], utx = sm[1][my][mx], uty = sm[2][my][mx];
-        const T sxx = sm[3][my][mx], sxy = sm[4][my][mx], syy = sm[5][my][mx];
-        const T ux = a.uprev[0][idx], uy = a.uprev[1][idx];
-        T vx = T(3) * utx + T(9) * (sxx * ux + sxy * uy) - T(3) * rt * ux;
-        T vy = T(3) * uty + T(9) * (sxy * ux + syy * uy) - T(3) * rt * uy;
-        // V_a += 2A sum_b D_b^T s~_ab
-        T f[5];
 #pragma unroll
-        for (int o = 0; o < 5; ++o) f[o] = sm[3][my][mx + o - 2];
-        vx += A2 * deriv_T(f, gx, nx, g.per[0]);
-#pragma unroll
-        for (int o = 0; o < 5; ++o) f[o] = sm[4][my + o - 2][mx];
-        vx += A2 * deriv_T(f, gy, ny, g.per[1]);
-#pragma unroll
-        for (int o = 0; o < 5; ++o) f[o] = sm[4][my][mx + o - 2];
-        vy += A2 * deriv_T(f, gx, nx, g.per[0]);
-#pragma unroll
-        for (int o = 0; o < 5; ++o) f[o] = sm[5][my + o - 2][mx];
-        vy += A2 * deriv_T(f, gy, ny, g.per[1]);
+    for (int ko = 0; ko < NR; ++ko) {
+        const int km = ko + H;
+        const int o = y0 + ko;
+        // x shifts of the strain moments (every lane)
+        const T xxl = from_left(mxx[km]), xxr = from_right(mxx[km]);
+        const T xyl = from_left(mxy[km]), xyr = from_right(mxy[km]);
+        T dxx, dxy, dyxy, dyyy;
+        if (IN) {
+            dxx = T(0.5) * (xxl - xxr);
+            dxy = T(0.5) * (xyl - xyr);
+            dyxy = T(0.5) * (mxy[km - 1] - mxy[km + 1]);
+            dyyy = T(0.5) * (myy[km - 1] - myy[km + 1]);
+        } else {
+            const T fxx[5] = {from_left(xxl), xxl, mxx[km], xxr, from_right(xxr)};
+            const T fxy[5] = {from_left(xyl), xyl, mxy[km], xyr, from_right(xyr)};
+            const T gxy[5] = {mxy[km - 2], mxy[km - 1], mxy[km], mxy[km + 1], mxy[km + 2]};
+            const T gyy[5] = {myy[km - 2], myy[km - 1], myy[km], myy[km + 1], myy[km + 2]};
+            dxx = deriv_T(fxx, c, nx, g.per[0]);
+            dxy = deriv_T(fxy, c, nx, g.per[0]);
+            dyxy = deriv_T(gxy, o, ny, g.per[1]);
+            dyyy = deriv_T(gyy, o, ny, g.per[1]);
+        }
+        if (!out_lane || o >= ny) continue;
+        const long long idx = c + (long long)o * g.sy;
+        const T ux = upx[ko], uy = upy[ko];
+        const T rt = mr[km];
+        T vx = T(3) * mux[km] + T(9) * (mxx[km] * ux + mxy[km] * uy) - T(3) * rt * ux;
+        T vy = T(3) * muy[km] + T(9) * (mxy[km] * ux + myy[km] * uy) - T(3) * rt * uy;
+        vx += A2 * dxx;
+        vx += A2 * dyxy;
+        vy += A2 * dxy;
+        vy += A2 * dyyy;
         a.Pout[idx] = rt;
         a.Vout[0][idx] = vx;
         a.Vout[1][idx] = vy;
@@ -457,14 +587,36 @@ __device__ __forceinline__ void adj2d_body(const AdjArgs<T> &a, int bx, int by) 
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_adj2d_batch(const AdjArgs<T> *args, const long long *tile0,
-                                                        int njobs) {
+__device__ __forceinline__ void adj2d_body(const AdjArgs<T> &a, int bx, int by) {
+    const int w = threadIdx.x >> 6;
+    const Geom &g = a.g;
+    const int nx = g.n[0], ny = g.n[1];
+    const int strip = bx * WPB + w;
+    if (strip >= (nx + SWA - 1) / SWA) return;
+    const int y0 = by * RYA, cmin = strip * SWA - 3;
+    if (cmin >= 1 && cmin + 63 <= nx - 2 && y0 >= 4 && y0 + RYA <= ny - 4) {
+        adj2d_rows<T, true, RYA>(a, strip, y0);
+    } else {
+#pragma unroll 1
+        for (int s = 0; s < RYA / RGA; ++s)
+            if (y0 + s * RGA < ny) adj2d_rows<T, false, RGA>(a, strip, y0 + s * RGA);
+    }
+}
+
+#ifndef LKS_ADJ2D_WAVES
+#define LKS_ADJ2D_WAVES 1
+#endif
+// the second bound asks for that many resident waves per SIMD (register budget)
+template <typename T>
+__global__ __launch_bounds__(kBlock, LKS_ADJ2D_WAVES) void k_adj2d_batch(const AdjArgs<T> *args,
+                                                                         const long long *tile0,
+                                                                         int njobs) {
     const long long b = blockIdx.x;
     const int j = job_of(tile0, njobs, b);
     const AdjArgs<T> &a = args[j];
-    const long long t = b - tile0[j];
-    const int nbx = (a.g.n[0] + TX - 1) / TX;
-    adj2d_body<T>(a, (int)(t % nbx), (int)(t / nbx));
+    const long long t = njobs == 1 ? b : b - tile0[j];  // one job: tile0 = {0}
+    const int nbx = adj2d_grid_x(a.g);
+    adj2d_body<T>(a, (int)(t % nbx), chunk_row((int)(t / nbx), adj2d_grid_y(a.g)));
 }
 
 long long fwd_blocks(const Geom &g, int lattice, int esz) {
@@ -479,7 +631,7 @@ long long xfer_blocks(int dim, long long cells, int esz) {
 }
 
 long long tiles2d_fwd(const Geom &g) { return (long long)fwd2d_grid_x(g) * fwd2d_grid_y(g); }
-long long tiles2d(const Geom &g) { return (long long)((g.n[0] + TX - 1) / TX) * ((g.n[1] + TY - 1) / TY); }
+long long tiles2d(const Geom &g) { return (long long)adj2d_grid_x(g) * adj2d_grid_y(g); }
 
 template <typename T>
 hipError_t launch_fwd2d_batch(const FwdArgs<T> *args, const long long *tile0, int njobs,

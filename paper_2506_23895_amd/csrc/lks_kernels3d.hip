@@ -291,7 +291,7 @@ __global__ __launch_bounds__(Tile3<T>::TX * Tile3<T>::TY) void k_fwd3d_batch(con
     const long long b = blockIdx.x;
     const int j = job_of3(tile0, njobs, b);
     const FwdArgs<T> &a = args[j];
-    const long long t = b - tile0[j];
+    const long long t = njobs == 1 ? b : b - tile0[j];  // one job: tile0 = {0}
     const long long ns = (a.mode & FWD_STENCIL) ? stencil_tiles3<T>(a.g) : 0;
     if (t >= ns) {  // extra blocks: transfer of the next step onto its footprint box
         transfer_box<T, 3, Tile3<T>::TX * Tile3<T>::TY>(a.des, a.mnext, a.box, a.knext, a.usnext, t - ns);
@@ -390,7 +390,7 @@ __global__ __launch_bounds__(kBlock) void k_adj3d_prep_batch(const AdjArgs<T> *a
                                                              const long long *blk0, int njobs) {
     const long long b = blockIdx.x;
     const int j = job_of3(blk0, njobs, b);
-    adj3d_prep_body<T>(args[j], b - blk0[j]);
+    adj3d_prep_body<T>(args[j], njobs == 1 ? b : b - blk0[j]);
 }
 
 // ================================== adjoint, z-marching part ==================================
@@ -588,7 +588,7 @@ __global__ __launch_bounds__(Tile3<T>::TX * Tile3<T>::TY) void k_adj3d_main_batc
     const int j = job_of3(tile0, njobs, b);
     const AdjArgs<T> &a = args[j];
     int bx, by, bz;
-    tile_coords3<T>(a.g, b - tile0[j], bx, by, bz);
+    tile_coords3<T>(a.g, njobs == 1 ? b : b - tile0[j], bx, by, bz);
     adj3d_main_body<T, Q>(a, bx, by, bz);
 }
 

@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kBlock) void k_sens_batch(const SensArgs<T> *args, 
         if (blk0[mid] <= b) lo = mid;
         else hi = mid - 1;
     }
-    sens_body<T>(args[lo], b - blk0[lo]);
+    sens_body<T>(args[lo], njobs == 1 ? b : b - blk0[lo]);
 }
 
 template <typename T>
