@@ -10,7 +10,12 @@ resident in HBM when the timed region starts (gamma lives in device memory).
 Default workload: D2Q9 channel, 1024x1024 analysis grid, 256x256 design grid rotating at
 2pi/1000, 10000 steps, checkpoint every 100 with recomputation, time-averaged drag, FP32.
 Other workloads: --workload c2 (2048x1024 forward only, 20000 steps), c1 (64x64 FP64, 400 steps),
-c4 (256^3 D3Q19, 3000 steps, checkpoint every 50).
+c4 (256^3 D3Q19, 3000 steps, checkpoint every 50), c5 (served sensitivity requests only).
+
+Served leg (in the default line as "served", or alone with --workload c5): seeded requests from
+the served mix (2D 128^2..1024^2 or 3D 64^3..160^3, 500..5000 steps) arrive as a Poisson stream
+at --rate requests/s; the continuous-batching server runs them, then the same list runs back to
+back through the single-job entry points.  Reports evals/s and p50/p99 latency of both.
 
 Prints ONE JSON line.  value = MLUPS = cells * time steps / seconds (forward + reverse, or
 forward only for c2).  The roofline object reports the dominant kernel's algorithmic bytes per
@@ -128,12 +133,38 @@ def cpu_baseline(wl: str, cfg: dict, gamma: np.ndarray) -> dict:
                       f"{'forward + reverse' if grad else 'forward'}, FP64 C oracle, {dt:.1f} s"}
 
 
+def served_leg(n_req: int, rate: float, seed: int = 5) -> dict:
+    """Continuous batching vs back-to-back plain solves on one seeded Poisson request list."""
+    from paper_2506_23895_amd.server import Request, Server, serve_plain, summarize
+    rng = np.random.default_rng(seed)
+    t, reqs = 0.0, []
+    for k in range(n_req):
+        t += float(rng.exponential(1.0 / rate))
+        cfg = I.served_job(rng)
+        reqs.append(Request(k, t, cfg, I.gamma_field(cfg["nd"], cfg["dim"], 100 + k)))
+    srv = Server()
+    served = summarize(srv.serve(reqs))
+    rounds = srv.rounds
+    srv.close()
+    plain = summarize(serve_plain(reqs))
+    out = {"requests": n_req, "rate_req_per_s": rate, "served": served, "plain": plain,
+           "rounds": rounds,
+           "mix": f"{sum(r.cfg['dim'] == 2 for r in reqs)} 2D / {sum(r.cfg['dim'] == 3 for r in reqs)} 3D, "
+                  f"{sum(r.cfg['nsteps'] for r in reqs)} steps in total"}
+    if served.get("evals_per_s") and plain.get("evals_per_s"):
+        out["speedup_vs_plain"] = round(served["evals_per_s"] / plain["evals_per_s"], 3)
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--requests", type=int, default=12, help="served leg: number of requests")
+    ap.add_argument("--rate", type=float, default=50.0, help="served leg: arrivals per second")
+    ap.add_argument("--no-served", action="store_true", help="skip the served leg")
     ap.add_argument("--nsteps", type=int, default=0, help="override the time horizon (profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--timing-every", type=int, default=8)
@@ -157,6 +188,20 @@ def main() -> int:
         torch.cuda.synchronize()
         print(f"[bench] calibration copy of {a.numel() * 4} bytes done", flush=True)
         del a, b
+
+    if args.workload == "c5":
+        t0 = time.perf_counter()
+        sv = served_leg(args.requests, args.rate)
+        dt = time.perf_counter() - t0
+        print(json.dumps({
+            "metric": "sens-evals/s served (continuous batching) + p50/p99 latency",
+            "value": sv["served"].get("evals_per_s"), "unit": "evals/s", "n_gpus": 1, "steps": 1,
+            "warmup": 0, "ms_per_step": round(dt * 1e3, 1), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "c5_served_mix", "requests": args.requests,
+                       "rate_req_per_s": args.rate, "parallelism": "single GPU"},
+            "served": sv}), flush=True)
+        return 0
 
     cfg, gamma = workload(args.workload, args.nsteps, args.period)
     tdtype = torch.float64 if cfg["precision"] == "F64" else torch.float32
@@ -233,6 +278,9 @@ def main() -> int:
         "roofline": roof,
     }
     solver.close()
+    if has_adj and not args.no_served:
+        print(f"[bench] served leg: {args.requests} requests at {args.rate}/s", flush=True)
+        line["served"] = served_leg(args.requests, args.rate)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, cfg, gamma)
     print(json.dumps(line), flush=True)

@@ -218,7 +218,8 @@ def config_c4(n_side: int = 256, nd_side: int = 96, precision: str = "F32", nste
 
 
 def served_job(rng: np.random.Generator, precision: str = "F32") -> dict:
-    """One request of the served mix: 2D 128^2..1024^2 or 3D 64^3..160^3, design at 40%."""
+    """One request of the served mix: 2D 128^2..1024^2 or 3D 64^3..160^3, design at 40%,
+    500..5000 steps, checkpoints every ceil(sqrt(steps)) steps."""
     is3d = bool(rng.integers(0, 2))
     rotate = bool(rng.integers(0, 2))
     nsteps = int(rng.integers(500, 5001))
@@ -243,4 +244,5 @@ def served_job(rng: np.random.Generator, precision: str = "F32") -> dict:
         bcs[2:] = [_bc("PERIODIC")] * 4
     return make_config(name=f"served_{dim}d_{s}", dim=dim, lattice=lat, n=n, nd=nd,
                        nu=nu_from_re(100, U_IN, d), nsteps=nsteps, motion=mot, bcs=bcs, obj=obj,
-                       u0=(U_IN, 0, 0), precision=precision, checkpoint_every=0)
+                       u0=(U_IN, 0, 0), precision=precision,
+                       checkpoint_every=int(math.ceil(math.sqrt(nsteps))))
