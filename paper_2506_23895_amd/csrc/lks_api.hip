@@ -371,9 +371,11 @@ struct Timed {
     lks_ctx *c;
     EventPair *ev = nullptr;
     hipStream_t s;
+    // launches on the recompute stream overlap the adjoint stream, so their event pairs would
+    // include queueing behind the other stream: only launches on the context's stream are timed
     Timed(lks_ctx *cc, int kind, hipStream_t st) : c(cc), s(st) {
         const long k = c->launches[kind]++;
-        if (c->every > 0 && k % c->every == 0 && c->pool_used < c->pool.size()) {
+        if (s == c->stream && c->every > 0 && k % c->every == 0 && c->pool_used < c->pool.size()) {
             ev = &c->pool[c->pool_used++];
             ev->kind = kind;
             (void)hipEventRecord(ev->a, s);

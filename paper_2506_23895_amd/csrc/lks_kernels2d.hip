@@ -282,15 +282,20 @@ __host__ __device__ inline int fwd2d_grid_x(const Geom &g) {
 }
 __host__ __device__ inline int fwd2d_grid_y(const Geom &g) { return (g.n[1] + RY - 1) / RY; }
 
-#ifndef LKS_TILE_ENDS_FIRST
-#define LKS_TILE_ENDS_FIRST 1
-#endif
-// row chunk of the r-th dispatched chunk row: alternately from both ends, so the waves that touch
-// the y faces (the slower general path) start early instead of forming the tail of the launch
-__device__ __forceinline__ int chunk_row(int r, int gy) {
-    if (!LKS_TILE_ENDS_FIRST) return r;
-    return (r & 1) ? gy - 1 - (r >> 1) : (r >> 1);
+// Blocks of a launch are dispatched round-robin over the 8 XCDs, each with its own L2.  Tile of
+// the t-th dispatched block out of T: XCD t % 8 gets a contiguous run of tiles (row-major), so
+// row chunks that share halo rows run on the same XCD close in time and the halos hit its L2.
+// Odd XCDs walk their run backwards, so the last run (the bottom face rows, slower code) starts
+// early instead of forming the tail of the launch.
+__device__ __forceinline__ long long xcd_tile(long long t, long long T) {
+    const long long q = T >> 3, r = T & 7, x = t & 7, l = t >> 3;
+    const long long n = q + (x < r ? 1 : 0);
+    return x * q + (x < r ? x : r) + ((x & 1) ? n - 1 - l : l);
 }
+
+// Row chunk of the r-th dispatched chunk row out of gy: alternately from both ends, so the waves
+// that touch the y faces (slower code) start early instead of forming the tail of the launch.
+__device__ __forceinline__ int chunk_row(int r, int gy) { return (r & 1) ? gy - 1 - (r >> 1) : (r >> 1); }
 
 // first tile of the job that owns flat tile b (tile0 ascending, tile0[0] = 0)
 __device__ __forceinline__ int job_of(const long long *tile0, int njobs, long long b) {
@@ -316,7 +321,8 @@ __global__ __launch_bounds__(kBlock) void k_fwd2d_batch(const FwdArgs<T> *args, 
         return;
     }
     const int nbx = fwd2d_grid_x(a.g);
-    fwd2d_body<T>(a, (int)(t % nbx), chunk_row((int)(t / nbx), fwd2d_grid_y(a.g)), t * WPB);
+    const long long tl = xcd_tile(t, ns);
+    fwd2d_body<T>(a, (int)(tl % nbx), (int)(tl / nbx), t * WPB);
 }
 
 // transposed difference operator along one axis at coordinate c: sum_r D[r][c] f(r), with f
