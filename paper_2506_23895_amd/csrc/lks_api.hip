@@ -273,6 +273,7 @@ struct lks_ctx {
     // reverse sweep: segments are recomputed on stream2 while the adjoint runs on stream
     hipStream_t stream2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_rec = nullptr, ev_adj = nullptr;
+    bool overlap = false;  // a recompute is in flight beside the adjoint launches (not timed)
 
     size_t esz() const { return L.esz; }
     int D() const { return d.dim; }
@@ -375,7 +376,8 @@ struct Timed {
     // include queueing behind the other stream: only launches on the context's stream are timed
     Timed(lks_ctx *cc, int kind, hipStream_t st) : c(cc), s(st) {
         const long k = c->launches[kind]++;
-        if (s == c->stream && c->every > 0 && k % c->every == 0 && c->pool_used < c->pool.size()) {
+        if (s == c->stream && !c->overlap && c->every > 0 && k % c->every == 0 &&
+            c->pool_used < c->pool.size()) {
             ev = &c->pool[c->pool_used++];
             ev->kind = kind;
             (void)hipEventRecord(ev->a, s);
@@ -791,8 +793,10 @@ int adjoint_impl(lks_ctx *c) {
                 if ((rc = launch_fwd_dev<T>(c, dra + (n - 1), ra[n - 1].mode, sr))) return rc;
             if (sr != c->stream) HIPCHK(c, hipEventRecord(c->ev_rec, sr));
         }
+        c->overlap = seg >= 1 && sr != c->stream;
         for (int n = n1; n >= n0; --n)
             if ((rc = launch_adj_dev<T>(c, daa + (n - 1), dsa + (n - 1)))) return rc;
+        c->overlap = false;
         if (sr != c->stream) HIPCHK(c, hipEventRecord(c->ev_adj, c->stream));
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
