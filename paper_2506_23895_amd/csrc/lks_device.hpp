@@ -12,6 +12,16 @@ enum { OBJ_NONE = -1, OBJ_POWER = 0, OBJ_DRAG = 1, OBJ_TORQUE = 2, OBJ_J1 = 3, O
 
 constexpr int kBlock = 256;
 
+// Pointers read out of an argument block are generic (flat) to the compiler, and flat loads count
+// against both the vector-memory and the LDS/scalar wait counters: every LDS or scalar wait would
+// then also drain all outstanding field loads.  Field accesses go through these casts to the global
+// address space, so they count against the vector-memory counter only.
+#define LKS_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ const LKS_GLOBAL T *gld(const T *p) { return (const LKS_GLOBAL T *)p; }
+template <typename T>
+__device__ __forceinline__ LKS_GLOBAL T *gst(T *p) { return (LKS_GLOBAL T *)p; }
+
 // wrap a coordinate onto a periodic axis; false if it leaves a non-periodic axis
 __device__ __forceinline__ bool wrapc(int &v, int n, int per) {
     if (v >= 0 && v < n) return true;

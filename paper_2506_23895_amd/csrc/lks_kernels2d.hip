@@ -73,9 +73,9 @@ __device__ __noinline__ double fwd2d_push(const FwdArgs<T> &a, int c, int o, T r
     const T v[4] = {rs, nux, nuy, T(0)};
     push_boundary<T, 2>(g, a.bc, c3, v, [&](const int p[3], const T pv[4]) {
         const long long pi = p[0] + p[1] * g.sy;
-        a.rout[pi] = pv[0];
-        a.uout[0][pi] = pv[1];
-        a.uout[1][pi] = pv[2];
+        gst(a.rout)[pi] = pv[0];
+        gst(a.uout[0])[pi] = pv[1];
+        gst(a.uout[1])[pi] = pv[2];
         if (obj_on && !obj_uses_kappa(a.obj.kind) && (!a.obj.mask || a.obj.mask[pi])) {
             const T pu[3] = {pv[1], pv[2], T(0)}, z3[3] = {0, 0, 0};
             j += obj_density<T>(a.obj, p[0], p[1], 0, (double)pv[0], pu, T(0), z3);
@@ -102,9 +102,14 @@ __device__ __forceinline__ void fwd2d_rows(const FwdArgs<T> &a, int strip, int y
     const int cmin = strip * SW - 2, cmax = cmin + 63;
     const bool xface = !IN && !g.per[0] && ((cmin <= 0 && 0 <= cmax) || (cmin <= nx - 1 && nx - 1 <= cmax));
     const bool out_lane = lane >= 2 && lane < 62 && (IN || (c < nx && !on_face(g, 0, c)));
-    const T *__restrict__ ux_in = a.uin[0];
-    const T *__restrict__ uy_in = a.uin[1];
-    const T *__restrict__ r_in = a.rin;
+    const LKS_GLOBAL T *__restrict__ ux_in = gld(a.uin[0]);
+    const LKS_GLOBAL T *__restrict__ uy_in = gld(a.uin[1]);
+    const LKS_GLOBAL T *__restrict__ r_in = gld(a.rin);
+    LKS_GLOBAL T *__restrict__ r_out = gst(a.rout);
+    LKS_GLOBAL T *__restrict__ ux_out = gst(a.uout[0]);
+    LKS_GLOBAL T *__restrict__ uy_out = gst(a.uout[1]);
+    const LKS_GLOBAL T *__restrict__ kst = gld(a.kstatic);
+    const LKS_GLOBAL uint8_t *__restrict__ omask = gld(a.obj.mask);
     // does this wave's rectangle meet the footprint box (wave-uniform)?
     const bool wbox = a.m.hi[0] >= strip * SW && a.m.lo[0] < strip * SW + SW && a.m.hi[1] >= y0 &&
                       a.m.lo[1] < y0 + RY;
@@ -119,9 +124,9 @@ __device__ __forceinline__ void fwd2d_rows(const FwdArgs<T> &a, int strip, int y
         const int o = y0 + k;
         if (wbox && c >= a.m.lo[0] && c <= a.m.hi[0] && o >= a.m.lo[1] && o <= a.m.hi[1]) {
             const long long bi = box_index(a.box, a.m, 2, c, o, 0);
-            kb[k] = a.kin[bi];
-            sbx[k] = a.usin[0][bi];
-            sby[k] = a.usin[1][bi];
+            kb[k] = gld(a.kin)[bi];
+            sbx[k] = gld(a.usin[0])[bi];
+            sby[k] = gld(a.usin[1])[bi];
         }
     }
 #pragma unroll
@@ -226,15 +231,15 @@ __device__ __forceinline__ void fwd2d_rows(const FwdArgs<T> &a, int strip, int y
                 const long long idx = c + (long long)o * g.sy;
                 T nux = mx + a.gf[0], nuy = my + a.gf[1];
                 if (brink) {
-                    const T ks = a.kstatic ? a.kstatic[idx] : T(0);
+                    const T ks = kst ? kst[idx] : T(0);
                     const T inv = rcp_t(T(1) + kap + ks);
                     nux = (nux + kap * us0) * inv;
                     nuy = (nuy + kap * us1) * inv;
                 }
-                a.rout[idx] = rs;
-                a.uout[0][idx] = nux;
-                a.uout[1][idx] = nuy;
-                if (obj_on && (kap != T(0) || !obj_uses_kappa(a.obj.kind)) && (!a.obj.mask || a.obj.mask[idx])) {
+                r_out[idx] = rs;
+                ux_out[idx] = nux;
+                uy_out[idx] = nuy;
+                if (obj_on && (kap != T(0) || !obj_uses_kappa(a.obj.kind)) && (!omask || omask[idx])) {
                     const T uv[3] = {nux, nuy, T(0)}, usv[3] = {us0, us1, T(0)};
                     jacc += obj_density<T>(a.obj, c, o, 0, (double)rs, uv, kap, usv);
                 }
@@ -252,7 +257,7 @@ __device__ __forceinline__ void fwd2d_rows(const FwdArgs<T> &a, int strip, int y
     if (obj_on) {
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) jacc += __shfl_xor(jacc, o, 64);
-        if (lane == 0) a.obj.partials[pslot] = jacc;
+        if (lane == 0) gst(a.obj.partials)[pslot] = jacc;
     }
 }
 
@@ -266,7 +271,7 @@ __device__ __forceinline__ void fwd2d_body(const FwdArgs<T> &a, int bx, int by, 
     const bool obj_on = a.obj.active && a.obj.kind != OBJ_NONE;
     const int nstrips = (nx + SW - 1) / SW;
     if (strip >= nstrips) {
-        if (obj_on && lane == 0) a.obj.partials[pslot] = 0.0;
+        if (obj_on && lane == 0) gst(a.obj.partials)[pslot] = 0.0;
         return;
     }
     const int y0 = by * RY, cmin = strip * SW - 2;
@@ -309,10 +314,10 @@ __device__ __forceinline__ int job_of(const long long *tile0, int njobs, long lo
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_fwd2d_batch(const FwdArgs<T> *args, const long long *tile0,
+__global__ __launch_bounds__(kBlock) void k_fwd2d_batch(const FwdArgs<T> *__restrict__ args, const long long *__restrict__ tile0,
                                                         int njobs) {
     const long long b = blockIdx.x;
-    const int j = job_of(tile0, njobs, b);
+    const int j = __builtin_amdgcn_readfirstlane(job_of(tile0, njobs, b));
     const FwdArgs<T> &a = args[j];
     const long long t = njobs == 1 ? b : b - tile0[j];  // one job: tile0 = {0}
     const long long ns = (a.mode & FWD_STENCIL) ? (long long)fwd2d_grid_x(a.g) * fwd2d_grid_y(a.g) : 0;
@@ -399,14 +404,14 @@ __device__ __forceinline__ void adj2d_rows(const AdjArgs<T> &a, int strip, int y
         lp[k] = lx[k] = ly[k] = kk[k] = ksx[k] = ksy[k] = T(0);
         if (!lv[k]) continue;
         const long long idx = cw + (long long)rw * g.sy;
-        lp[k] = a.Pin[idx];
-        lx[k] = a.Vin[0][idx];
-        ly[k] = a.Vin[1][idx];
+        lp[k] = gld(a.Pin)[idx];
+        lx[k] = gld(a.Vin[0])[idx];
+        ly[k] = gld(a.Vin[1])[idx];
         if (wbox && in_box(a.m, 2, cw, rw, 0)) {
             const long long bi = box_index(a.box, a.m, 2, cw, rw, 0);
-            kk[k] = a.kbox[bi];
-            ksx[k] = a.usbox[0][bi];
-            ksy[k] = a.usbox[1][bi];
+            kk[k] = gld(a.kbox)[bi];
+            ksx[k] = gld(a.usbox[0])[bi];
+            ksy[k] = gld(a.usbox[1])[bi];
         }
     }
     // velocities the outputs and kappa_bar need, requested with the lambda rows
@@ -418,11 +423,11 @@ __device__ __forceinline__ void adj2d_rows(const AdjArgs<T> &a, int strip, int y
         upx[ko] = upy[ko] = ucx[ko] = ucy[ko] = T(0);
         if (!out_lane || o >= ny) continue;
         const long long idx = c + (long long)o * g.sy;
-        upx[ko] = a.uprev[0][idx];
-        upy[ko] = a.uprev[1][idx];
+        upx[ko] = gld(a.uprev[0])[idx];
+        upy[ko] = gld(a.uprev[1])[idx];
         if (wbox && in_box(a.m, 2, c, o, 0)) {
-            ucx[ko] = a.ucur[0][idx];
-            ucy[ko] = a.ucur[1][idx];
+            ucx[ko] = gld(a.ucur[0])[idx];
+            ucy[ko] = gld(a.ucur[1])[idx];
         }
     }
     if (obj_on) {
@@ -432,7 +437,7 @@ __device__ __forceinline__ void adj2d_rows(const AdjArgs<T> &a, int strip, int y
             if (!lv[k]) continue;
             if (!IN) wrapc(rw, ny, g.per[1]);
             const long long idx = cw + (long long)rw * g.sy;
-            if (a.obj.mask && !a.obj.mask[idx]) continue;
+            if (a.obj.mask && !gld(a.obj.mask)[idx]) continue;
             if (kobj && kk[k] == T(0)) continue;  // kappa objectives vanish off the body
             const double us[3] = {(double)ksx[k], (double)ksy[k], 0.0};
             double dP, dV[3];
@@ -490,7 +495,7 @@ __device__ __forceinline__ void adj2d_rows(const AdjArgs<T> &a, int strip, int y
             }
         }
         if (brink) {  // rw is wrapped here whenever lv[k] holds
-            const T ks = (a.kstatic && lv[k]) ? a.kstatic[cw + (long long)rw * g.sy] : T(0);
+            const T ks = (a.kstatic && lv[k]) ? gld(a.kstatic)[cw + (long long)rw * g.sy] : T(0);
             const T inv = rcp_t(T(1) + kk[k] + ks);
             Vx *= inv;
             Vy *= inv;
@@ -505,12 +510,12 @@ __device__ __forceinline__ void adj2d_rows(const AdjArgs<T> &a, int strip, int y
             const long long bi = box_index(a.box, a.m, 2, c, o, 0);
             const T ux = ucx[kp - H - 1], uy = ucy[kp - H - 1];
             double kb = -((double)Vx * ((double)ux - (double)ksx[k]) + (double)Vy * ((double)uy - (double)ksy[k]));
-            if (kobj && (!a.obj.mask || a.obj.mask[idx])) {
+            if (kobj && (!a.obj.mask || gld(a.obj.mask)[idx])) {
                 const double uu[3] = {(double)ux, (double)uy, 0.0};
                 const double uss[3] = {(double)ksx[k], (double)ksy[k], 0.0};
                 kb += sc * obj_dkappa(a.obj, c, o, 0, uu, uss);
             }
-            a.kbar[bi] = (T)kb;
+            gst(a.kbar)[bi] = (T)kb;
         }
     }
 
@@ -586,9 +591,9 @@ __device__ __forceinline__ void adj2d_rows(const AdjArgs<T> &a, int strip, int y
         vx += A2 * dyxy;
         vy += A2 * dxy;
         vy += A2 * dyyy;
-        a.Pout[idx] = rt;
-        a.Vout[0][idx] = vx;
-        a.Vout[1][idx] = vy;
+        gst(a.Pout)[idx] = rt;
+        gst(a.Vout[0])[idx] = vx;
+        gst(a.Vout[1])[idx] = vy;
     }
 }
 
@@ -614,11 +619,11 @@ __device__ __forceinline__ void adj2d_body(const AdjArgs<T> &a, int bx, int by) 
 #endif
 // the second bound asks for that many resident waves per SIMD (register budget)
 template <typename T>
-__global__ __launch_bounds__(kBlock, LKS_ADJ2D_WAVES) void k_adj2d_batch(const AdjArgs<T> *args,
-                                                                         const long long *tile0,
+__global__ __launch_bounds__(kBlock, LKS_ADJ2D_WAVES) void k_adj2d_batch(const AdjArgs<T> *__restrict__ args,
+                                                                         const long long *__restrict__ tile0,
                                                                          int njobs) {
     const long long b = blockIdx.x;
-    const int j = job_of(tile0, njobs, b);
+    const int j = __builtin_amdgcn_readfirstlane(job_of(tile0, njobs, b));
     const AdjArgs<T> &a = args[j];
     const long long t = njobs == 1 ? b : b - tile0[j];  // one job: tile0 = {0}
     const int nbx = adj2d_grid_x(a.g);

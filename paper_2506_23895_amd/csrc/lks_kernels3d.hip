@@ -45,9 +45,12 @@ __device__ constexpr double wq(int i) {
 
 template <typename T>
 struct Tile3 {};
+#ifndef LKS_FWD3D_ZC
+#define LKS_FWD3D_ZC 32
+#endif
 template <>
 struct Tile3<float> {
-    static constexpr int TX = 32, TY = 8, ZC = 32;
+    static constexpr int TX = 32, TY = 8, ZC = LKS_FWD3D_ZC;  // z planes marched per block
 };
 template <>
 struct Tile3<double> {
@@ -66,12 +69,47 @@ __device__ __forceinline__ T dcoord(T fm2, T fm1, T f0, T fp1, T fp2, int c, int
 }
 
 // ================================== forward ==================================================
+template <int Q>
+__device__ constexpr int opp(int q) {  // index of -c_q
+    for (int r = 0; r < Q; ++r)
+        if (cq<Q>(r, 0) == -cq<Q>(q, 0) && cq<Q>(r, 1) == -cq<Q>(q, 1) && cq<Q>(r, 2) == -cq<Q>(q, 2)) return r;
+    return q;
+}
+
+// face nodes written from interior node c3 (value v), with their objective contribution
+template <typename T>
+__device__ __noinline__ double fwd3d_push(const FwdArgs<T> &a, int x, int y, int z, T r, T u0, T u1,
+                                          T u2, bool obj_on) {
+    const Geom &g = a.g;
+    double j = 0.0;
+    const int c3[3] = {x, y, z};
+    const T v[4] = {r, u0, u1, u2};
+    push_boundary<T, 3>(g, a.bc, c3, v, [&](const int p[3], const T pv[4]) {
+        const long long pi = p[0] + p[1] * g.sy + p[2] * g.sz;
+        a.rout[pi] = pv[0];
+        a.uout[0][pi] = pv[1];
+        a.uout[1][pi] = pv[2];
+        a.uout[2][pi] = pv[3];
+        if (obj_on && !obj_uses_kappa(a.obj.kind) && (!a.obj.mask || a.obj.mask[pi])) {
+            const T pu[3] = {pv[1], pv[2], pv[3]}, z3[3] = {0, 0, 0};
+            j += obj_density<T>(a.obj, p[0], p[1], p[2], (double)pv[0], pu, T(0), z3);
+        }
+    });
+    return j;
+}
+
+// one-sided second-order derivative at a face node: into the domain from f0 (lo) or (hi)
+template <typename T>
+__device__ __forceinline__ T d_lo(T f0, T f1, T f2) { return T(-1.5) * f0 + T(2) * f1 - T(0.5) * f2; }
+template <typename T>
+__device__ __forceinline__ T d_hi(T f0, T f1, T f2) { return T(1.5) * f0 - T(2) * f1 + T(0.5) * f2; }
+
 template <typename T, int Q>
 __device__ __forceinline__ void fwd3d_body(const FwdArgs<T> &a, int bx, int by, int bz, long long blin) {
     constexpr int TX = Tile3<T>::TX, TY = Tile3<T>::TY, ZC = Tile3<T>::ZC, NT = TX * TY;
     constexpr int UX = TX + 4, UY = TY + 4, UP = UX * UY;  // velocity plane, halo 2
     constexpr int EX = TX + 2, EY = TY + 2, EP = EX * EY;  // E_i plane, halo 1
-    constexpr int NU = (UP + NT - 1) / NT, NR = (EP + NT - 1) / NT;
+    constexpr int NU = (UP + NT - 1) / NT, NE = (EP + NT - 1) / NT;
     __shared__ T su[5][3][UP];
     __shared__ T sE[Q][EP];
     __shared__ double sh[NT / 64];
@@ -81,28 +119,94 @@ __device__ __forceinline__ void fwd3d_body(const FwdArgs<T> &a, int bx, int by, 
     const int tid = threadIdx.x;
     const int x0 = bx * TX, y0 = by * TY, zs = bz * ZC;
     const int ze = min(zs + ZC, nz);
-    const int ox = tid % TX, oy = tid / TX;
     const T A = a.A;
+    // block-uniform: E or output nodes of the block on or next to a non-periodic x / y face
+    const bool xface = !g.per[0] && (x0 - 1 <= 1 || x0 + TX >= nx - 2);
+    const bool yface = !g.per[1] && (y0 - 1 <= 1 || y0 + TY >= ny - 2);
+    const bool obj_on = a.obj.active && a.obj.kind != OBJ_NONE;
+    const bool kobj = obj_on && obj_uses_kappa(a.obj.kind);
 
-    T ureg[NU][3];
-    T rreg[NR];
-    auto fetch_u = [&](int zp) {
+    // per-thread offsets, computed once: velocity-plane slots (x, y wrapped; -1 off the domain)
+    long long uoff[NU];
+#pragma unroll
+    for (int k = 0; k < NU; ++k) {
+        const int i = tid + k * NT;
+        uoff[k] = -1;
+        if (i >= UP) continue;
+        int gx = x0 - 2 + i % UX, gy = y0 - 2 + i / UX;
+        if (wrapc(gx, nx, g.per[0]) && wrapc(gy, ny, g.per[1])) uoff[k] = gx + (long long)gy * g.sy;
+    }
+    // E slots: index of the node in a velocity plane, offset of its rho, face bits (1 x = 0,
+    // 2 x = nx - 1, 4 y = 0, 8 y = ny - 1); -1 for slots off the domain (their E is never pulled)
+    int ec0[NE], efl[NE];
+    long long roff[NE];
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+        const int i = tid + k * NT;
+        efl[k] = -1;
+        ec0[k] = 0;
+        roff[k] = 0;
+        if (i >= EP) continue;
+        const int lx = i % EX, ly = i / EX;
+        int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+        if (!wrapc(gx, nx, g.per[0]) || !wrapc(gy, ny, g.per[1])) continue;
+        ec0[k] = (ly + 1) * UX + (lx + 1);
+        roff[k] = gx + (long long)gy * g.sy;
+        int f = 0;
+        if (!g.per[0]) f |= (gx == 0 ? 1 : 0) | (gx == nx - 1 ? 2 : 0);
+        if (!g.per[1]) f |= (gy == 0 ? 4 : 0) | (gy == ny - 1 ? 8 : 0);
+        efl[k] = f;
+    }
+    // this thread's output column
+    const int ox = tid % TX, oy = tid / TX;
+    const int gxo = x0 + ox, gyo = y0 + oy;
+    const bool out_ok = gxo < nx && gyo < ny && !on_face(g, 0, gxo) && !on_face(g, 1, gyo);
+    const long long ooff = gxo + (long long)gyo * g.sy;
+    const bool xybox = a.m.hi[0] >= x0 && a.m.lo[0] < x0 + TX && a.m.hi[1] >= y0 && a.m.lo[1] < y0 + TY;
+    const bool obox = out_ok && gxo >= a.m.lo[0] && gxo <= a.m.hi[0] && gyo >= a.m.lo[1] && gyo <= a.m.hi[1];
+    const int per2 = g.per[2];
+
+    // two register sets of velocity planes: the plane loaded in one iteration is committed to the
+    // LDS ring in the next, so its loads have a whole iteration to arrive
+    T ua[NU][3], ub[NU][3];
+    T rreg[NE];
+    // argument fields used in the loop, held locally: stores through the output pointers could
+    // otherwise alias the argument block and force it to be re-read
+    const LKS_GLOBAL T *__restrict__ uin0 = gld(a.uin[0]);
+    const LKS_GLOBAL T *__restrict__ uin1 = gld(a.uin[1]);
+    const LKS_GLOBAL T *__restrict__ uin2 = gld(a.uin[2]);
+    const LKS_GLOBAL T *__restrict__ rin = gld(a.rin);
+    LKS_GLOBAL T *__restrict__ rout = gst(a.rout);
+    LKS_GLOBAL T *__restrict__ uout0 = gst(a.uout[0]);
+    LKS_GLOBAL T *__restrict__ uout1 = gst(a.uout[1]);
+    LKS_GLOBAL T *__restrict__ uout2 = gst(a.uout[2]);
+    const LKS_GLOBAL T *__restrict__ kin = gld(a.kin);
+    const LKS_GLOBAL T *__restrict__ usin0 = gld(a.usin[0]);
+    const LKS_GLOBAL T *__restrict__ usin1 = gld(a.usin[1]);
+    const LKS_GLOBAL T *__restrict__ usin2 = gld(a.usin[2]);
+    const LKS_GLOBAL T *__restrict__ kst = gld(a.kstatic);
+    const LKS_GLOBAL uint8_t *__restrict__ omask = gld(a.obj.mask);
+    const StepMotion m = a.m;    // motion and box geometry of this step, held in registers
+    const BoxGeom box = a.box;
+    const T gf0 = a.gf[0], gf1 = a.gf[1], gf2 = a.gf[2];
+    const long long sz = g.sz;
+    // loads are unconditional (slots off the domain read element 0 and select zero), so the
+    // wait counters can follow each load and a plane's loads overlap the previous plane's work
+    auto fetch_u = [&](T(&ureg)[NU][3], int zp) {
         int zw = zp;
         const bool zin = wrapc(zw, nz, g.per[2]);
+        const long long zo = zin ? (long long)zw * sz : 0;
 #pragma unroll
         for (int k = 0; k < NU; ++k) {
-            const int i = tid + k * NT;
-            ureg[k][0] = ureg[k][1] = ureg[k][2] = T(0);
-            if (i >= UP || !zin) continue;
-            int gx = x0 - 2 + i % UX, gy = y0 - 2 + i / UX;
-            if (!wrapc(gx, nx, g.per[0]) || !wrapc(gy, ny, g.per[1])) continue;
-            const long long idx = gx + gy * g.sy + zw * g.sz;
-            ureg[k][0] = a.uin[0][idx];
-            ureg[k][1] = a.uin[1][idx];
-            ureg[k][2] = a.uin[2][idx];
+            const bool ok = zin && uoff[k] >= 0;
+            const long long o = ok ? uoff[k] + zo : 0;
+            const T v0 = uin0[o], v1 = uin1[o], v2 = uin2[o];
+            ureg[k][0] = ok ? v0 : T(0);
+            ureg[k][1] = ok ? v1 : T(0);
+            ureg[k][2] = ok ? v2 : T(0);
         }
     };
-    auto commit_u = [&](int zp) {
+    auto commit_u = [&](T(&ureg)[NU][3], int zp) {
         const int sl = ring5(zp);
 #pragma unroll
         for (int k = 0; k < NU; ++k) {
@@ -117,85 +221,104 @@ __device__ __forceinline__ void fwd3d_body(const FwdArgs<T> &a, int bx, int by, 
     auto fetch_r = [&](int zp) {
         int zw = zp;
         const bool zin = wrapc(zw, nz, g.per[2]);
+        const long long zo = zin ? (long long)zw * sz : 0;
 #pragma unroll
-        for (int k = 0; k < NR; ++k) {
-            const int i = tid + k * NT;
-            rreg[k] = T(0);
-            if (i >= EP || !zin) continue;
-            int gx = x0 - 1 + i % EX, gy = y0 - 1 + i / EX;
-            if (!wrapc(gx, nx, g.per[0]) || !wrapc(gy, ny, g.per[1])) continue;
-            rreg[k] = a.rin[gx + gy * g.sy + zw * g.sz];
+        for (int k = 0; k < NE; ++k) {
+            const bool ok = zin && efl[k] >= 0;
+            const T v = rin[ok ? roff[k] + zo : 0];
+            rreg[k] = ok ? v : T(0);
         }
     };
 
     for (int zp = zs - 3; zp <= zs + 1; ++zp) {
-        fetch_u(zp);
-        commit_u(zp);
+        fetch_u(ua, zp);
+        commit_u(ua, zp);
     }
     fetch_r(zs - 1);
+    fetch_u(ua, zs + 2);  // committed by the first iteration
     __syncthreads();
 
     T acc[3][4];
 #pragma unroll
     for (int t = 0; t < 3; ++t) acc[t][0] = acc[t][1] = acc[t][2] = acc[t][3] = T(0);
     double jacc = 0.0;
-    const bool obj_on = a.obj.active && a.obj.kind != OBJ_NONE;
 
-    for (int zc = zs - 1; zc <= ze; ++zc) {
-        T rcur[NR];
+    auto step = [&](int zc, T(&ucommit)[NU][3], T(&uload)[NU][3]) {
+        const int zo = zc - 1;  // output plane finished in this iteration
+        const bool zout = zo >= zs && zo < ze && !on_face(g, 2, zo);
+        // footprint values and kappa_s of this thread's output node, requested early
+        T kap = T(0), us0 = T(0), us1 = T(0), us2 = T(0), ks = T(0);
+        if (xybox) {  // block-uniform
+            const bool inb = zout && obox && zo >= m.lo[2] && zo <= m.hi[2];
+            const long long bi = inb ? box_index(box, m, 3, gxo, gyo, zo) : 0;
+            const T k0 = kin[bi], s0v = usin0[bi], s1v = usin1[bi], s2v = usin2[bi];
+            kap = inb ? k0 : T(0);
+            us0 = inb ? s0v : T(0);
+            us1 = inb ? s1v : T(0);
+            us2 = inb ? s2v : T(0);
+        }
+        if (kst) {  // block-uniform
+            const bool ok = zout && out_ok;
+            const T kv = kst[ok ? ooff + (long long)zo * sz : 0];
+            ks = ok ? kv : T(0);
+        }
+        T rcur[NE];
 #pragma unroll
-        for (int k = 0; k < NR; ++k) rcur[k] = rreg[k];
-        fetch_u(zc + 3);  // in flight during the stencil work below
+        for (int k = 0; k < NE; ++k) rcur[k] = rreg[k];
+        fetch_u(uload, zc + 4);  // committed by the next iteration
         fetch_r(zc + 1);
         int zw = zc;
         const bool zin = wrapc(zw, nz, g.per[2]);
         if (zin) {
             const int s0 = ring5(zc), sm1 = ring5(zc - 1), sp1 = ring5(zc + 1), sm2 = ring5(zc - 2),
                       sp2 = ring5(zc + 2);
+            const bool zlo = !g.per[2] && zw == 0, zhi = !g.per[2] && zw == nz - 1;
 #pragma unroll
-            for (int k = 0; k < NR; ++k) {
-                const int i = tid + k * NT;
-                if (i >= EP) continue;
-                const int lx = i % EX, ly = i / EX;
-                const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
-                if (!g.per[0] && (gx < 0 || gx >= nx)) continue;
-                if (!g.per[1] && (gy < 0 || gy >= ny)) continue;
-                const int c0 = (ly + 1) * UX + (lx + 1);
+            for (int k = 0; k < NE; ++k) {
+                if (efl[k] < 0) continue;
+                const int c0 = ec0[k];
                 T u[3], du[3][3];  // du[c][b] = d u_c / d x_b
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const T *p = su[s0][c];
                     u[c] = p[c0];
-                    du[c][0] = dcoord(c0 >= 2 ? p[c0 - 2] : T(0), p[c0 - 1], p[c0], p[c0 + 1],
-                                      p[c0 + 2], gx, nx, g.per[0]);
-                    du[c][1] = dcoord(ly + 1 >= 2 ? p[c0 - 2 * UX] : T(0), p[c0 - UX], p[c0],
-                                      p[c0 + UX], ly + 3 < UY ? p[c0 + 2 * UX] : T(0), gy, ny,
-                                      g.per[1]);
-                    du[c][2] = dcoord(su[sm2][c][c0], su[sm1][c][c0], p[c0], su[sp1][c][c0],
-                                      su[sp2][c][c0], zw, nz, g.per[2]);
+                    du[c][0] = T(0.5) * (p[c0 + 1] - p[c0 - 1]);
+                    du[c][1] = T(0.5) * (p[c0 + UX] - p[c0 - UX]);
+                    du[c][2] = T(0.5) * (su[sp1][c][c0] - su[sm1][c][c0]);
+                    if (xface && (efl[k] & 3))
+                        du[c][0] = (efl[k] & 1) ? d_lo(u[c], p[c0 + 1], p[c0 + 2]) : d_hi(u[c], p[c0 - 1], p[c0 - 2]);
+                    if (yface && (efl[k] & 12))
+                        du[c][1] = (efl[k] & 4) ? d_lo(u[c], p[c0 + UX], p[c0 + 2 * UX])
+                                                : d_hi(u[c], p[c0 - UX], p[c0 - 2 * UX]);
+                    if (zlo) du[c][2] = d_lo(u[c], su[sp1][c][c0], su[sp2][c][c0]);
+                    if (zhi) du[c][2] = d_hi(u[c], su[sm1][c][c0], su[sm2][c][c0]);
                 }
-                const T r = rcur[k];
-                const T a0 = r - T(1.5) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+                const T a0 = rcur[k] - T(1.5) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
                 T tt[3][3];
 #pragma unroll
-                for (int p = 0; p < 3; ++p)
+                for (int pp = 0; pp < 3; ++pp)
 #pragma unroll
-                    for (int q = 0; q < 3; ++q)
-                        tt[p][q] = T(4.5) * u[p] * u[q] + A * (du[p][q] + du[q][p]);
+                    for (int qq = pp; qq < 3; ++qq)
+                        tt[pp][qq] = T(4.5) * u[pp] * u[qq] + A * (du[pp][qq] + du[qq][pp]);
+                const int i = tid + k * NT;
+                sE[0][i] = T(wq<Q>(0)) * a0;
+                // +c and -c share the even part a0 + c.T.c; the odd part 3 c.u changes sign
 #pragma unroll
-                for (int q = 0; q < Q; ++q) {
+                for (int q = 1; q < Q; ++q) {
                     constexpr int dummy = 0;
                     (void)dummy;
+                    if (opp<Q>(q) < q) continue;
                     const int cx = cq<Q>(q, 0), cy = cq<Q>(q, 1), cz = cq<Q>(q, 2);
-                    T v = a0 + T(3) * (T(cx) * u[0] + T(cy) * u[1] + T(cz) * u[2]);
-                    v += T(cx * cx) * tt[0][0] + T(cy * cy) * tt[1][1] + T(cz * cz) * tt[2][2];
-                    v += T(2 * cx * cy) * tt[0][1] + T(2 * cx * cz) * tt[0][2] + T(2 * cy * cz) * tt[1][2];
-                    sE[q][i] = T(wq<Q>(q)) * v;
+                    T ev = a0 + T(cx * cx) * tt[0][0] + T(cy * cy) * tt[1][1] + T(cz * cz) * tt[2][2];
+                    ev += T(2 * cx * cy) * tt[0][1] + T(2 * cx * cz) * tt[0][2] + T(2 * cy * cz) * tt[1][2];
+                    const T od = T(3) * (T(cx) * u[0] + T(cy) * u[1] + T(cz) * u[2]);
+                    sE[q][i] = T(wq<Q>(q)) * (ev + od);
+                    sE[opp<Q>(q)][i] = T(wq<Q>(q)) * (ev - od);
                 }
             }
         }
         __syncthreads();
-        commit_u(zc + 3);
+        commit_u(ucommit, zc + 3);
         // pull: output (x, y, zo) takes E_i from (x - cx, y - cy) in plane zo - cz
         if (zin) {
 #pragma unroll
@@ -204,49 +327,32 @@ __device__ __forceinline__ void fwd3d_body(const FwdArgs<T> &a, int bx, int by, 
                 const T e = sE[q][(oy + 1 - cy) * EX + (ox + 1 - cx)];
                 const int t = cz + 1;  // cz = -1 -> plane zc - 1, 0 -> zc, +1 -> zc + 1
                 acc[t][0] += e;
-                acc[t][1] += T(cx) * e;
-                acc[t][2] += T(cy) * e;
-                acc[t][3] += T(cz) * e;
+                if (cx) acc[t][1] += T(cx) * e;
+                if (cy) acc[t][2] += T(cy) * e;
+                if (cz) acc[t][3] += T(cz) * e;
             }
         }
-        const int zo = zc - 1;
-        const int gx = x0 + ox, gy = y0 + oy;
-        if (zo >= zs && zo < ze && gx < nx && gy < ny && !on_face(g, 0, gx) && !on_face(g, 1, gy) &&
-            !on_face(g, 2, zo)) {
+        if (zout && out_ok) {
             const T rs = acc[0][0];
-            T kap = 0, us[3] = {0, 0, 0};
-            if (in_box(a.m, 3, gx, gy, zo)) {
-                const long long bi = box_index(a.box, a.m, 3, gx, gy, zo);
-                kap = a.kin[bi];
-                us[0] = a.usin[0][bi];
-                us[1] = a.usin[1][bi];
-                us[2] = a.usin[2][bi];
+            T nu0 = acc[0][1] + gf0, nu1 = acc[0][2] + gf1, nu2 = acc[0][3] + gf2;
+            if (xybox || kst) {
+                const T inv = T(1) / (T(1) + kap + ks);
+                nu0 = (nu0 + kap * us0) * inv;
+                nu1 = (nu1 + kap * us1) * inv;
+                nu2 = (nu2 + kap * us2) * inv;
             }
-            const long long idx = gx + gy * g.sy + zo * g.sz;
-            const T ks = a.kstatic ? a.kstatic[idx] : T(0);
-            const T inv = T(1) / (T(1) + kap + ks);
-            T nu[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) nu[c] = (acc[0][1 + c] + kap * us[c] + a.gf[c]) * inv;
-            a.rout[idx] = rs;
-            a.uout[0][idx] = nu[0];
-            a.uout[1][idx] = nu[1];
-            a.uout[2][idx] = nu[2];
-            if (obj_on && (!a.obj.mask || a.obj.mask[idx]))
-                jacc += obj_density<T>(a.obj, gx, gy, zo, (double)rs, nu, kap, us);
-            const int c3[3] = {gx, gy, zo};
-            const T v[4] = {rs, nu[0], nu[1], nu[2]};
-            push_boundary<T, 3>(g, a.bc, c3, v, [&](const int p[3], const T pv[4]) {
-                const long long pi = p[0] + p[1] * g.sy + p[2] * g.sz;
-                a.rout[pi] = pv[0];
-                a.uout[0][pi] = pv[1];
-                a.uout[1][pi] = pv[2];
-                a.uout[2][pi] = pv[3];
-                if (obj_on && (!a.obj.mask || a.obj.mask[pi])) {
-                    const T pu[3] = {pv[1], pv[2], pv[3]}, z3[3] = {0, 0, 0};
-                    jacc += obj_density<T>(a.obj, p[0], p[1], p[2], (double)pv[0], pu, T(0), z3);
-                }
-            });
+            const long long idx = ooff + (long long)zo * sz;
+            rout[idx] = rs;
+            uout0[idx] = nu0;
+            uout1[idx] = nu1;
+            uout2[idx] = nu2;
+            if (obj_on && (!kobj || kap != T(0)) && (!omask || omask[idx])) {
+                const T nu[3] = {nu0, nu1, nu2}, us[3] = {us0, us1, us2};
+                jacc += obj_density<T>(a.obj, gxo, gyo, zo, (double)rs, nu, kap, us);
+            }
+            const bool zadj = !per2 && (zo == 1 || zo == nz - 2);
+            if ((xface && (gxo == 1 || gxo == nx - 2)) || (yface && (gyo == 1 || gyo == ny - 2)) || zadj)
+                jacc += fwd3d_push<T>(a, gxo, gyo, zo, rs, nu0, nu1, nu2, obj_on);
         }
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
@@ -255,6 +361,10 @@ __device__ __forceinline__ void fwd3d_body(const FwdArgs<T> &a, int bx, int by, 
             acc[2][c] = T(0);
         }
         __syncthreads();
+    };
+    for (int zc = zs - 1; zc <= ze; zc += 2) {
+        step(zc, ua, ub);
+        if (zc + 1 <= ze) step(zc + 1, ub, ua);
     }
     if (obj_on) store_partial<NT>(a.obj, jacc, blin, sh);
 }
@@ -285,11 +395,11 @@ __device__ __forceinline__ long long stencil_tiles3(const Geom &g) {
 }
 
 template <typename T, int Q>
-__global__ __launch_bounds__(Tile3<T>::TX * Tile3<T>::TY) void k_fwd3d_batch(const FwdArgs<T> *args,
-                                                                            const long long *tile0,
+__global__ __launch_bounds__(Tile3<T>::TX * Tile3<T>::TY) void k_fwd3d_batch(const FwdArgs<T> *__restrict__ args,
+                                                                            const long long *__restrict__ tile0,
                                                                             int njobs) {
     const long long b = blockIdx.x;
-    const int j = job_of3(tile0, njobs, b);
+    const int j = __builtin_amdgcn_readfirstlane(job_of3(tile0, njobs, b));
     const FwdArgs<T> &a = args[j];
     const long long t = njobs == 1 ? b : b - tile0[j];  // one job: tile0 = {0}
     const long long ns = (a.mode & FWD_STENCIL) ? stencil_tiles3<T>(a.g) : 0;
@@ -386,10 +496,10 @@ __device__ __forceinline__ void adj3d_prep_body(const AdjArgs<T> &a, long long b
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_adj3d_prep_batch(const AdjArgs<T> *args,
-                                                             const long long *blk0, int njobs) {
+__global__ __launch_bounds__(kBlock) void k_adj3d_prep_batch(const AdjArgs<T> *__restrict__ args,
+                                                             const long long *__restrict__ blk0, int njobs) {
     const long long b = blockIdx.x;
-    const int j = job_of3(blk0, njobs, b);
+    const int j = __builtin_amdgcn_readfirstlane(job_of3(blk0, njobs, b));
     adj3d_prep_body<T>(args[j], njobs == 1 ? b : b - blk0[j]);
 }
 
@@ -581,11 +691,11 @@ __device__ __forceinline__ void adj3d_main_body(const AdjArgs<T> &a, int bx, int
 }
 
 template <typename T, int Q>
-__global__ __launch_bounds__(Tile3<T>::TX * Tile3<T>::TY) void k_adj3d_main_batch(const AdjArgs<T> *args,
-                                                                                 const long long *tile0,
+__global__ __launch_bounds__(Tile3<T>::TX * Tile3<T>::TY) void k_adj3d_main_batch(const AdjArgs<T> *__restrict__ args,
+                                                                                 const long long *__restrict__ tile0,
                                                                                  int njobs) {
     const long long b = blockIdx.x;
-    const int j = job_of3(tile0, njobs, b);
+    const int j = __builtin_amdgcn_readfirstlane(job_of3(tile0, njobs, b));
     const AdjArgs<T> &a = args[j];
     int bx, by, bz;
     tile_coords3<T>(a.g, njobs == 1 ? b : b - tile0[j], bx, by, bz);

@@ -103,7 +103,7 @@ __device__ __forceinline__ void sens_body(const SensArgs<T> &a, long long blk) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_sens_batch(const SensArgs<T> *args, const long long *blk0,
+__global__ __launch_bounds__(kBlock) void k_sens_batch(const SensArgs<T> *__restrict__ args, const long long *__restrict__ blk0,
                                                        int njobs) {
     const long long b = blockIdx.x;
     int lo = 0, hi = njobs - 1;
@@ -112,6 +112,7 @@ __global__ __launch_bounds__(kBlock) void k_sens_batch(const SensArgs<T> *args, 
         if (blk0[mid] <= b) lo = mid;
         else hi = mid - 1;
     }
+    lo = __builtin_amdgcn_readfirstlane(lo);
     sens_body<T>(args[lo], njobs == 1 ? b : b - blk0[lo]);
 }
 
