@@ -201,7 +201,7 @@ int plan(const lks_desc *d, Layout &L, std::string *err) {
     L.b_traj = L.fwd_only ? 0 : (size_t)L.banks * (L.K + 1) * D * L.F * e;
     L.b_box = L.fwd_only ? 0 : (size_t)L.banks * L.K * nf * L.box.cells * e;
     L.b_xring = 2 * nf * L.box.cells * e;  // kappa, u_S of the steps outside the stored segment
-    L.b_kbar = L.fwd_only ? 0 : (size_t)L.box.cells * e;
+    L.b_kbar = L.fwd_only ? 0 : (size_t)2 * L.box.cells * e;  // kappa_bar of steps n (n even / odd)
     L.b_adj = L.fwd_only ? 0 : 2 * nf * L.F * e;
     L.b_final = nf * L.F * e;
     L.b_design = (size_t)L.nd * (3 * e + 2 * 8);  // gamma, kref, sens out; kprime, G
@@ -504,6 +504,32 @@ int launch_xfer_dev(lks_ctx *c, const lks::FwdArgs<T> *dargs, hipStream_t s) {
     return LKS_OK;
 }
 
+// one adjoint step; in 2D its launch also carries the gather of the previous adjoint step
+// (extra blocks, host copy `ha` says how many)
+template <typename T>
+int launch_adj_fused(lks_ctx *c, const lks::AdjArgs<T> *dargs, const lks::AdjArgs<T> &ha) {
+    hipError_t e;
+    {
+        Timed t(c, 1, c->stream);
+        e = lks::launch_adj2d_batch<T>(dargs, c->tile0, 1,
+                                       lks::tiles2d(c->L.g) + (ha.sens ? ha.sens_blocks : 0), c->stream);
+    }
+    HIPCHK(c, e);
+    return LKS_OK;
+}
+
+template <typename T>
+int launch_sens_dev(lks_ctx *c, const lks::SensArgs<T> *dsens) {
+    hipError_t e;
+    {
+        Timed t(c, 2, c->stream);
+        e = lks::launch_sens_batch<T>(dsens, c->tile0, 1, (c->L.nd + lks::kBlockHost - 1) / lks::kBlockHost,
+                                      c->stream);
+    }
+    HIPCHK(c, e);
+    return LKS_OK;
+}
+
 template <typename T>
 int launch_adj_dev(lks_ctx *c, const lks::AdjArgs<T> *dargs, const lks::SensArgs<T> *dsens) {
     hipError_t e;
@@ -698,7 +724,7 @@ lks::AdjArgs<T> make_adj_args(lks_ctx *c, int n, int j, int acur) {
     const T *b = box_slot<T>(c, false, j - 1, bank);
     a.kbox = b;
     for (int k = 0; k < 3; ++k) a.usbox[k] = k < D ? b + (1 + k) * L.box.cells : nullptr;
-    a.kbar = reinterpret_cast<T *>(c->kbar);
+    a.kbar = reinterpret_cast<T *>(c->kbar) + (long long)(n & 1) * L.box.cells;
     a.box = L.box;
     a.m = L.steps[n];
     a.obj = obj_params(c, n);
@@ -712,7 +738,7 @@ lks::AdjArgs<T> make_adj_args(lks_ctx *c, int n, int j, int acur) {
 template <typename T>
 lks::SensArgs<T> make_sens_args(lks_ctx *c, int n) {
     lks::SensArgs<T> sa{};
-    sa.kbar = reinterpret_cast<T *>(c->kbar);
+    sa.kbar = reinterpret_cast<T *>(c->kbar) + (long long)(n & 1) * c->L.box.cells;
     sa.box = c->L.box;
     sa.m = c->L.steps[n];
     sa.des = design<T>(c);
@@ -764,6 +790,16 @@ int adjoint_impl(lks_ctx *c) {
                 acur = 1 - acur;
             }
         }
+        if (D == 2) {  // each adjoint launch also runs the gather of the step after it (kappa_bar
+                       // of consecutive steps lives in alternate halves of the kappa_bar buffer)
+            const auto *dsa_dev = reinterpret_cast<const lks::SensArgs<T> *>(
+                c->argdev + (size_t)nfa * sizeof(lks::FwdArgs<T>) + (size_t)N * sizeof(lks::AdjArgs<T>));
+            const long long sb = (L.nd + lks::kBlockHost - 1) / lks::kBlockHost;
+            for (int n = 1; n < N; ++n) {
+                aa[n - 1].sens = dsa_dev + n;
+                aa[n - 1].sens_blocks = sb;
+            }
+        }
         if ((rc = upload_args(c, bytes))) return rc;
     }
     const auto *dra = reinterpret_cast<const lks::FwdArgs<T> *>(c->argdev);
@@ -794,11 +830,15 @@ int adjoint_impl(lks_ctx *c) {
             if (sr != c->stream) HIPCHK(c, hipEventRecord(c->ev_rec, sr));
         }
         c->overlap = seg >= 1 && sr != c->stream;
-        for (int n = n1; n >= n0; --n)
-            if ((rc = launch_adj_dev<T>(c, daa + (n - 1), dsa + (n - 1)))) return rc;
+        for (int n = n1; n >= n0; --n) {
+            if (D == 2) rc = launch_adj_fused<T>(c, daa + (n - 1), aa[n - 1]);
+            else rc = launch_adj_dev<T>(c, daa + (n - 1), dsa + (n - 1));
+            if (rc) return rc;
+        }
         c->overlap = false;
         if (sr != c->stream) HIPCHK(c, hipEventRecord(c->ev_adj, c->stream));
     }
+    if (D == 2 && (rc = launch_sens_dev<T>(c, dsa))) return rc;  // gather of step 1
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (sr != c->stream) HIPCHK(c, hipStreamSynchronize(sr));
     if ((rc = flush_timing(c))) return rc;

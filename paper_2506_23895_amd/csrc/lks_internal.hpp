@@ -83,6 +83,9 @@ struct FwdArgs {
 enum { FWD_STENCIL = 1, FWD_TRANSFER_NEXT = 2 };
 
 template <typename T>
+struct SensArgs;
+
+template <typename T>
 struct AdjArgs {
     Geom g;
     BCParams<T> bc;
@@ -102,6 +105,8 @@ struct AdjArgs {
     ObjParams obj;
     T *Ps;              // 3D only: (P*, V*) scratch fields between the two adjoint kernels
     T *Vs[3];
+    const SensArgs<T> *sens;  // 2D: gather of the previous adjoint step run by extra blocks, or null
+    long long sens_blocks;
 };
 
 template <typename T>

@@ -627,6 +627,11 @@ __global__ __launch_bounds__(kBlock, LKS_ADJ2D_WAVES) void k_adj2d_batch(const A
     const AdjArgs<T> &a = args[j];
     const long long t = njobs == 1 ? b : b - tile0[j];  // one job: tile0 = {0}
     const int nbx = adj2d_grid_x(a.g);
+    const long long na = (long long)nbx * adj2d_grid_y(a.g);
+    if (t >= na) {  // extra blocks: sensitivity gather of the previous adjoint step
+        sens_body<T>(*a.sens, t - na);
+        return;
+    }
     adj2d_body<T>(a, (int)(t % nbx), chunk_row((int)(t / nbx), adj2d_grid_y(a.g)));
 }
 

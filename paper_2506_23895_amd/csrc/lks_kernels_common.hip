@@ -52,57 +52,6 @@ __global__ __launch_bounds__(kBlock) void k_init(const InitArgs<T> a) {
 }
 
 template <typename T>
-__device__ __forceinline__ void sens_body(const SensArgs<T> &a, long long blk) {
-    const long long ndn = (long long)a.des.nd[0] * a.des.nd[1] * a.des.nd[2];
-    const long long i = blk * kBlock + threadIdx.x;
-    if (i >= ndn) return;
-    const int ix = (int)(i % a.des.nd[0]);
-    const int iy = (int)((i / a.des.nd[0]) % a.des.nd[1]);
-    const int iz = (int)(i / ((long long)a.des.nd[0] * a.des.nd[1]));
-    const double d0 = ix - a.des.xiG[0], d1 = iy - a.des.xiG[1],
-                 d2 = (a.dim == 3) ? iz - a.des.xiG[2] : 0.0;
-    double xr[3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-        xr[r] = a.m.R[3 * r] * d0 + a.m.R[3 * r + 1] * d1 + a.m.R[3 * r + 2] * d2 + a.m.xG[r];
-    const double s = a.des.weight == 1 ? 1.0 : 2.0;
-    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-    for (int r = 0; r < a.dim; ++r) {
-        lo[r] = max(a.m.lo[r], (int)ceil(xr[r] - s));
-        hi[r] = min(a.m.hi[r], (int)floor(xr[r] + s));
-    }
-    // the weight is a product over analysis axes and the support spans at most 2s + 1 nodes per
-    // axis: per-axis weights first, then every load of a z-plane issued together
-    constexpr int MW = 5;
-    T wx[MW], wy[MW];
-#pragma unroll
-    for (int t = 0; t < MW; ++t) {
-        wx[t] = lo[0] + t <= hi[0] ? wk<T>(a.des.weight, (T)(lo[0] + t - xr[0])) : T(0);
-        wy[t] = lo[1] + t <= hi[1] ? wk<T>(a.des.weight, (T)(lo[1] + t - xr[1])) : T(0);
-    }
-    double acc = 0.0;
-    for (int z = lo[2]; z <= hi[2]; ++z) {
-        const T wz = (a.dim == 3) ? wk<T>(a.des.weight, (T)(z - xr[2])) : T(1);
-        if (wz == T(0)) continue;
-        T kv[MW][MW];
-#pragma unroll
-        for (int ty = 0; ty < MW; ++ty)
-#pragma unroll
-            for (int tx = 0; tx < MW; ++tx)
-                kv[ty][tx] = (wx[tx] != T(0) && wy[ty] != T(0))
-                                 ? a.kbar[box_index(a.box, a.m, a.dim, lo[0] + tx, lo[1] + ty, z)]
-                                 : T(0);
-#pragma unroll
-        for (int ty = 0; ty < MW; ++ty)
-#pragma unroll
-            for (int tx = 0; tx < MW; ++tx)
-                if (wx[tx] != T(0) && wy[ty] != T(0))
-                    acc += (double)(wx[tx] * wy[ty] * wz) * (double)kv[ty][tx];
-    }
-    a.G[i] += acc;
-}
-
-template <typename T>
 __global__ __launch_bounds__(kBlock) void k_sens_batch(const SensArgs<T> *__restrict__ args, const long long *__restrict__ blk0,
                                                        int njobs) {
     const long long b = blockIdx.x;
