@@ -121,12 +121,14 @@ __device__ __forceinline__ void fwd2d_rows(const FwdArgs<T> &a, int strip, int y
 #pragma unroll
     for (int k = 0; k < RY; ++k) {
         kb[k] = sbx[k] = sby[k] = T(0);
-        const int o = y0 + k;
-        if (wbox && c >= a.m.lo[0] && c <= a.m.hi[0] && o >= a.m.lo[1] && o <= a.m.hi[1]) {
-            const long long bi = box_index(a.box, a.m, 2, c, o, 0);
-            kb[k] = gld(a.kin)[bi];
-            sbx[k] = gld(a.usin[0])[bi];
-            sby[k] = gld(a.usin[1])[bi];
+        if (wbox) {  // wave-uniform; unconditional loads from a clamped index, then select
+            const int o = y0 + k;
+            const bool inb = c >= a.m.lo[0] && c <= a.m.hi[0] && o >= a.m.lo[1] && o <= a.m.hi[1];
+            const long long bi = inb ? box_index(a.box, a.m, 2, c, o, 0) : 0;
+            const T k0 = gld(a.kin)[bi], s0 = gld(a.usin[0])[bi], s1 = gld(a.usin[1])[bi];
+            kb[k] = inb ? k0 : T(0);
+            sbx[k] = inb ? s0 : T(0);
+            sby[k] = inb ? s1 : T(0);
         }
     }
 #pragma unroll
@@ -138,18 +140,25 @@ __device__ __forceinline__ void fwd2d_rows(const FwdArgs<T> &a, int strip, int y
             const long long idx = c + (long long)yw * g.sy;
             ux[k] = ux_in[idx];
             uy[k] = uy_in[idx];
-        } else if (cin && wrapc(yw, ny, g.per[1])) {
-            const long long idx = cw + yw * g.sy;
-            ux[k] = ux_in[idx];
-            uy[k] = uy_in[idx];
+        } else {
+            const bool ok = cin && wrapc(yw, ny, g.per[1]);
+            const long long idx = ok ? cw + (long long)yw * g.sy : 0;
+            const T v0 = ux_in[idx], v1 = uy_in[idx];
+            ux[k] = ok ? v0 : T(0);
+            uy[k] = ok ? v1 : T(0);
         }
     }
 #pragma unroll
     for (int k = 0; k < RY + 2; ++k) {
         int yw = y0 - 1 + k;
         rv[k] = T(0);
-        if (IN) rv[k] = r_in[c + (long long)yw * g.sy];
-        else if (cin && wrapc(yw, ny, g.per[1])) rv[k] = r_in[cw + yw * g.sy];
+        if (IN) {
+            rv[k] = r_in[c + (long long)yw * g.sy];
+        } else {
+            const bool ok = cin && wrapc(yw, ny, g.per[1]);
+            const T v = r_in[ok ? cw + (long long)yw * g.sy : 0];
+            rv[k] = ok ? v : T(0);
+        }
     }
 
     T acc_r[3] = {0, 0, 0}, acc_m[3] = {0, 0, 0};  // own column: rho*, m_y* for rows r-1, r, r+1
@@ -263,7 +272,9 @@ __device__ __forceinline__ void fwd2d_rows(const FwdArgs<T> &a, int strip, int y
 
 template <typename T>
 __device__ __forceinline__ void fwd2d_body(const FwdArgs<T> &a, int bx, int by, long long slot0) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // the wave index is uniform across a wave: in a scalar register, every per-wave decision below
+    // (strip, interior test, footprint test) is a scalar branch instead of an exec-masked region
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const Geom &g = a.g;
     const int nx = g.n[0], ny = g.n[1];
     const int strip = bx * WPB + w;
@@ -395,23 +406,36 @@ __device__ __forceinline__ void adj2d_rows(const AdjArgs<T> &a, int strip, int y
     const bool brink = wbox || a.kstatic != nullptr;
 
     // ---- lambda rows (and kappa, u_S where the footprint box meets the wave) ----
+    // loads are unconditional from clamped indices (element 0 where a node is off the domain or
+    // off the box) and select zero afterwards: no load sits behind a per-lane branch, so the wait
+    // counters can follow each one
     T lp[NL], lx[NL], ly[NL], kk[NL], ksx[NL], ksy[NL];
     bool lv[NL];
+    const LKS_GLOBAL T *__restrict__ Pin = gld(a.Pin);
+    const LKS_GLOBAL T *__restrict__ Vin0 = gld(a.Vin[0]);
+    const LKS_GLOBAL T *__restrict__ Vin1 = gld(a.Vin[1]);
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
         int rw = yl0 + k;
         lv[k] = cin && (IN || wrapc(rw, ny, g.per[1]));
-        lp[k] = lx[k] = ly[k] = kk[k] = ksx[k] = ksy[k] = T(0);
-        if (!lv[k]) continue;
-        const long long idx = cw + (long long)rw * g.sy;
-        lp[k] = gld(a.Pin)[idx];
-        lx[k] = gld(a.Vin[0])[idx];
-        ly[k] = gld(a.Vin[1])[idx];
-        if (wbox && in_box(a.m, 2, cw, rw, 0)) {
-            const long long bi = box_index(a.box, a.m, 2, cw, rw, 0);
-            kk[k] = gld(a.kbox)[bi];
-            ksx[k] = gld(a.usbox[0])[bi];
-            ksy[k] = gld(a.usbox[1])[bi];
+        const long long idx = lv[k] ? cw + (long long)rw * g.sy : 0;
+        const T p0 = Pin[idx], v0 = Vin0[idx], v1 = Vin1[idx];
+        lp[k] = lv[k] ? p0 : T(0);
+        lx[k] = lv[k] ? v0 : T(0);
+        ly[k] = lv[k] ? v1 : T(0);
+        kk[k] = ksx[k] = ksy[k] = T(0);
+    }
+    if (wbox) {  // wave-uniform
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            int rw = yl0 + k;
+            if (!IN) wrapc(rw, ny, g.per[1]);
+            const bool inb = lv[k] && in_box(a.m, 2, cw, rw, 0);
+            const long long bi = inb ? box_index(a.box, a.m, 2, cw, rw, 0) : 0;
+            const T k0 = gld(a.kbox)[bi], s0 = gld(a.usbox[0])[bi], s1 = gld(a.usbox[1])[bi];
+            kk[k] = inb ? k0 : T(0);
+            ksx[k] = inb ? s0 : T(0);
+            ksy[k] = inb ? s1 : T(0);
         }
     }
     // velocities the outputs and kappa_bar need, requested with the lambda rows
@@ -420,17 +444,21 @@ __device__ __forceinline__ void adj2d_rows(const AdjArgs<T> &a, int strip, int y
 #pragma unroll
     for (int ko = 0; ko < NR; ++ko) {
         const int o = y0 + ko;
-        upx[ko] = upy[ko] = ucx[ko] = ucy[ko] = T(0);
-        if (!out_lane || o >= ny) continue;
-        const long long idx = c + (long long)o * g.sy;
-        upx[ko] = gld(a.uprev[0])[idx];
-        upy[ko] = gld(a.uprev[1])[idx];
-        if (wbox && in_box(a.m, 2, c, o, 0)) {
-            ucx[ko] = gld(a.ucur[0])[idx];
-            ucy[ko] = gld(a.ucur[1])[idx];
+        const bool ok = out_lane && o < ny;
+        const long long idx = ok ? c + (long long)o * g.sy : 0;
+        const T p0 = gld(a.uprev[0])[idx], p1 = gld(a.uprev[1])[idx];
+        upx[ko] = ok ? p0 : T(0);
+        upy[ko] = ok ? p1 : T(0);
+        ucx[ko] = ucy[ko] = T(0);
+        if (wbox) {  // wave-uniform
+            const bool okb = ok && in_box(a.m, 2, c, o, 0);
+            const long long ib = okb ? idx : 0;
+            const T c0 = gld(a.ucur[0])[ib], c1 = gld(a.ucur[1])[ib];
+            ucx[ko] = okb ? c0 : T(0);
+            ucy[ko] = okb ? c1 : T(0);
         }
     }
-    if (obj_on) {
+    if (obj_on && (wbox || !kobj)) {  // kappa objectives are non-zero on the footprint only
 #pragma unroll
         for (int k = 0; k < NL; ++k) {
             int rw = yl0 + k;
@@ -599,7 +627,7 @@ __device__ __forceinline__ void adj2d_rows(const AdjArgs<T> &a, int strip, int y
 
 template <typename T>
 __device__ __forceinline__ void adj2d_body(const AdjArgs<T> &a, int bx, int by) {
-    const int w = threadIdx.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar branches
     const Geom &g = a.g;
     const int nx = g.n[0], ny = g.n[1];
     const int strip = bx * WPB + w;
