@@ -374,7 +374,10 @@ __device__ __forceinline__ T deriv_T(const T f[5], int c, int n, int per) {
 // Every lane that a needed P* sits on has both neighbours inside the wave, so the boundary
 // seeds of column-adjacent faces come from lane shifts as well.
 constexpr int SWA = 58;  // output columns per adjoint wave strip
-constexpr int RYA = 4;   // output rows per wave
+#ifndef LKS_ADJ2D_RY
+#define LKS_ADJ2D_RY 2
+#endif
+constexpr int RYA = LKS_ADJ2D_RY;  // output rows per wave
 constexpr int RGA = 2;   // rows per pass in waves that touch a face or wrap
 
 __host__ __device__ inline int adj2d_grid_x(const Geom &g) {
