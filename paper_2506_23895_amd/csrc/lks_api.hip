@@ -258,8 +258,9 @@ struct lks_ctx {
     size_t pool_used = 0;
     // continuous batching: where this context stands in its evaluation
     struct Cursor {
-        int phase = 0;  // 0 idle, 1 forward, 2 reverse setup, 3 adjoint, 4 restore, 5 recompute, 6 done
+        int phase = 0;  // 0 idle, 1 forward, 2 reverse setup, 3 reverse (adjoint + recompute), 6 done
         int n = 0, seg = 0, cur = 0, acur = 0;
+        int ready = 0, rseg = -1, rn = 0;  // reverse sweep: recompute of the previous segment
     } cs;
     double *jn_host = nullptr;  // pinned
     int *flag_host = nullptr;   // pinned
@@ -974,7 +975,7 @@ struct lks_batch {
 
 namespace {
 
-enum { PH_IDLE = 0, PH_FWD = 1, PH_ADJ_BEGIN = 2, PH_ADJ = 3, PH_REC_BEGIN = 4, PH_REC = 5, PH_DONE = 6 };
+enum { PH_IDLE = 0, PH_FWD = 1, PH_ADJ_BEGIN = 2, PH_ADJ = 3, PH_DONE = 6 };
 
 template <typename T>
 struct RoundLists {
@@ -1086,50 +1087,57 @@ int plan_step(lks_ctx *c, RoundLists<T> &R, int *rc) {
         cs.seg = S - 1;
         cs.n = seg_hi(cs.seg);
         cs.acur = 0;
+        cs.ready = S - 1;  // lowest segment whose trajectory bank is complete (the forward wrote S-1)
+        cs.rseg = -1;      // segment being recomputed, -1 when none
         cs.phase = PH_ADJ;
     }
-    if (cs.phase == PH_REC_BEGIN) {
-        const T *ck = reinterpret_cast<const T *>(c->field(c->ckpt, (long long)cs.seg * (1 + D)));
-        T *t0[3];
-        traj_slot<T>(c, bank_of(c, cs.seg), 0, t0);
-        if ((*rc = copy_fields<T>(c, st[0].r, ck, 1))) return 0;
-        if ((*rc = copy_fields<T>(c, t0[0], ck + L.F, D))) return 0;
-        R.pre[li].push_back(make_xfer_args<T>(c, seg_lo(cs.seg), rec_loc<T>(c, cs.seg, seg_lo(cs.seg))));
-        R.ptiles[li].push_back(fwd_tiles(c, lks::FWD_TRANSFER_NEXT));
-        cs.cur = 0;
-        cs.n = seg_lo(cs.seg);
-        cs.phase = PH_REC;
-    }
-    if (cs.phase == PH_REC) {
-        const int n = cs.n, j = n - cs.seg * K;
-        T *uin[3], *uout[3];
-        traj_slot<T>(c, bank_of(c, cs.seg), j - 1, uin);
-        traj_slot<T>(c, bank_of(c, cs.seg), j, uout);
-        R.fwd[li].push_back(make_fwd_args<T>(c, n, st[cs.cur].r, uin, st[1 - cs.cur].r, uout,
-                                             rec_loc<T>(c, cs.seg, n),
-                                             n < seg_hi(cs.seg) ? rec_loc<T>(c, cs.seg, n + 1) : nullptr, false));
-        R.ftiles[li].push_back(fwd_tiles(c, R.fwd[li].back().mode));
-        cs.cur = 1 - cs.cur;
-        cs.n = n + 1;
-        if (cs.n > seg_hi(cs.seg)) {
-            cs.phase = PH_ADJ;
-            cs.n = seg_hi(cs.seg);
-        }
-        return 0;
-    }
     if (cs.phase == PH_ADJ) {
-        const int n = cs.n, j = n - cs.seg * K;
-        R.adj[li].push_back(make_adj_args<T>(c, n, j, cs.acur));
-        R.atiles[li].push_back(adj_tiles(c));
-        R.ablk[li].push_back((L.ncell + lks::kBlockHost - 1) / lks::kBlockHost);
-        R.sens.push_back(make_sens_args<T>(c, n));
-        R.sblk.push_back((L.nd + lks::kBlockHost - 1) / lks::kBlockHost);
-        cs.acur = 1 - cs.acur;
-        cs.n = n - 1;
-        if (cs.n < seg_lo(cs.seg)) {
-            cs.seg -= 1;
-            if (cs.seg < 0) return 2;
-            cs.phase = PH_REC_BEGIN;
+        // Reverse rounds: one recompute step of segment seg-1 (into the other bank) and one adjoint
+        // step of segment seg, in the same round.  Segment seg-1 is restored once the adjoint of
+        // seg+1, which used its bank, is done; the adjoint of a segment waits for its recompute.
+        if (cs.rseg < 0 && cs.seg - 1 >= 0 && cs.seg - 1 < cs.ready) {
+            cs.rseg = cs.seg - 1;
+            const T *ck = reinterpret_cast<const T *>(c->field(c->ckpt, (long long)cs.rseg * (1 + D)));
+            T *t0[3];
+            traj_slot<T>(c, bank_of(c, cs.rseg), 0, t0);
+            if ((*rc = copy_fields<T>(c, st[0].r, ck, 1))) return 0;
+            if ((*rc = copy_fields<T>(c, t0[0], ck + L.F, D))) return 0;
+            R.pre[li].push_back(make_xfer_args<T>(c, seg_lo(cs.rseg), rec_loc<T>(c, cs.rseg, seg_lo(cs.rseg))));
+            R.ptiles[li].push_back(fwd_tiles(c, lks::FWD_TRANSFER_NEXT));
+            cs.cur = 0;
+            cs.rn = seg_lo(cs.rseg);
+        }
+        if (cs.rseg >= 0) {
+            const int n = cs.rn, j = n - cs.rseg * K;
+            T *uin[3], *uout[3];
+            traj_slot<T>(c, bank_of(c, cs.rseg), j - 1, uin);
+            traj_slot<T>(c, bank_of(c, cs.rseg), j, uout);
+            R.fwd[li].push_back(make_fwd_args<T>(c, n, st[cs.cur].r, uin, st[1 - cs.cur].r, uout,
+                                                 rec_loc<T>(c, cs.rseg, n),
+                                                 n < seg_hi(cs.rseg) ? rec_loc<T>(c, cs.rseg, n + 1) : nullptr,
+                                                 false));
+            R.ftiles[li].push_back(fwd_tiles(c, R.fwd[li].back().mode));
+            cs.cur = 1 - cs.cur;
+            cs.rn = n + 1;
+            if (cs.rn > seg_hi(cs.rseg)) {
+                cs.ready = cs.rseg;
+                cs.rseg = -1;
+            }
+        }
+        if (cs.ready <= cs.seg) {
+            const int n = cs.n, j = n - cs.seg * K;
+            R.adj[li].push_back(make_adj_args<T>(c, n, j, cs.acur));
+            R.atiles[li].push_back(adj_tiles(c));
+            R.ablk[li].push_back((L.ncell + lks::kBlockHost - 1) / lks::kBlockHost);
+            R.sens.push_back(make_sens_args<T>(c, n));
+            R.sblk.push_back((L.nd + lks::kBlockHost - 1) / lks::kBlockHost);
+            cs.acur = 1 - cs.acur;
+            cs.n = n - 1;
+            if (cs.n < seg_lo(cs.seg)) {
+                cs.seg -= 1;
+                if (cs.seg < 0) return 2;
+                cs.n = seg_hi(cs.seg);
+            }
         }
         return 0;
     }

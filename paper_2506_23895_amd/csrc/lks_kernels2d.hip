@@ -29,8 +29,6 @@ __device__ constexpr int cy(int i) {
 __device__ constexpr double wt(int i) { return i == 0 ? W0 : (i < 5 ? WA : WD); }
 }  // namespace d2q9
 
-constexpr int TX = 64, TY = 8;
-
 // ---- lane shifts within a 64-wide wavefront (DPP wave_shr:1 / wave_shl:1; edge lanes read 0) ----
 __device__ __forceinline__ int dpp_l(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, true); }
 __device__ __forceinline__ int dpp_r(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, true); }
