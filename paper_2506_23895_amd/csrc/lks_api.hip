@@ -193,6 +193,10 @@ int plan(const lks_desc *d, Layout &L, std::string *err) {
     L.box.bsy = bn[0];
     L.box.bsz = (long long)bn[0] * bn[1];
     L.box.cells = (long long)bn[0] * bn[1] * bn[2];
+    // the kernels decompose cell, design-node and box indices with 32-bit arithmetic
+    if ((long long)g.n[0] * g.n[1] * g.n[2] >= (1LL << 31) || (long long)d->nd[0] * d->nd[1] * d->nd[2] >= (1LL << 31) ||
+        L.box.cells >= (1LL << 31))
+        return fail(err, LKS_EINVAL, "grid, design grid and footprint box must each hold fewer than 2^31 nodes");
 
     const size_t e = L.esz;
     const size_t nf = 1 + D;

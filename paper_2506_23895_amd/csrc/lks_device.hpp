@@ -162,7 +162,9 @@ __device__ __forceinline__ void transfer_box(const Design<T> &des, const StepMot
     const int ex = m.hi[0] - m.lo[0] + 1, ey = m.hi[1] - m.lo[1] + 1;
     const int ez = DIM == 3 ? m.hi[2] - m.lo[2] + 1 : 1;
     if (cell >= (long long)ex * ey * ez) return;
-    const int bx = (int)(cell % ex), by = (int)((cell / ex) % ey), bz = (int)(cell / ((long long)ex * ey));
+    // 32-bit division: box extents are validated below 2^31 cells at create
+    const unsigned cu = (unsigned)cell, uex = (unsigned)ex, uey = (unsigned)ey;
+    const int bx = (int)(cu % uex), by = (int)((cu / uex) % uey), bz = (int)(cu / (uex * uey));
     T kap, us[3];
     gather_kappa<T, DIM>(des, m, m.lo[0] + bx, m.lo[1] + by, DIM == 3 ? m.lo[2] + bz : 0, kap, us);
     const long long bi = bx + by * box.bsy + (DIM == 3 ? bz * box.bsz : 0LL);
@@ -367,9 +369,8 @@ __device__ __forceinline__ void sens_body(const SensArgs<T> &a, long long blk) {
     const long long ndn = (long long)a.des.nd[0] * a.des.nd[1] * a.des.nd[2];
     const long long i = blk * kBlock + threadIdx.x;
     if (i >= ndn) return;
-    const int ix = (int)(i % a.des.nd[0]);
-    const int iy = (int)((i / a.des.nd[0]) % a.des.nd[1]);
-    const int iz = (int)(i / ((long long)a.des.nd[0] * a.des.nd[1]));
+    const unsigned iu = (unsigned)i, n0 = (unsigned)a.des.nd[0], n1 = (unsigned)a.des.nd[1];
+    const int ix = (int)(iu % n0), iy = (int)((iu / n0) % n1), iz = (int)(iu / (n0 * n1));  // < 2^31
     const double d0 = ix - a.des.xiG[0], d1 = iy - a.des.xiG[1],
                  d2 = (a.dim == 3) ? iz - a.des.xiG[2] : 0.0;
     double xr[3];

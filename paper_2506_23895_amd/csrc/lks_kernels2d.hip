@@ -336,7 +336,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd2d_batch(const FwdArgs<T> *__rest
     }
     const int nbx = fwd2d_grid_x(a.g);
     const long long tl = xcd_tile(t, ns);
-    fwd2d_body<T>(a, (int)(tl % nbx), (int)(tl / nbx), t * WPB);
+    fwd2d_body<T>(a, (int)((unsigned)tl % (unsigned)nbx), (int)((unsigned)tl / (unsigned)nbx), t * WPB);
 }
 
 // transposed difference operator along one axis at coordinate c: sum_r D[r][c] f(r), with f
@@ -661,7 +661,7 @@ __global__ __launch_bounds__(kBlock, LKS_ADJ2D_WAVES) void k_adj2d_batch(const A
         sens_body<T>(*a.sens, t - na);
         return;
     }
-    adj2d_body<T>(a, (int)(t % nbx), chunk_row((int)(t / nbx), adj2d_grid_y(a.g)));
+    adj2d_body<T>(a, (int)((unsigned)t % (unsigned)nbx), chunk_row((int)((unsigned)t / (unsigned)nbx), adj2d_grid_y(a.g)));
 }
 
 long long fwd_blocks(const Geom &g, int lattice, int esz) {

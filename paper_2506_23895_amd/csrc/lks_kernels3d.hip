@@ -383,9 +383,10 @@ template <typename T>
 __device__ __forceinline__ void tile_coords3(const Geom &g, long long t, int &bx, int &by, int &bz) {
     const int nbx = (g.n[0] + Tile3<T>::TX - 1) / Tile3<T>::TX;
     const int nby = (g.n[1] + Tile3<T>::TY - 1) / Tile3<T>::TY;
-    bx = (int)(t % nbx);
-    by = (int)((t / nbx) % nby);
-    bz = (int)(t / ((long long)nbx * nby));
+    const unsigned tu = (unsigned)t;
+    bx = (int)(tu % (unsigned)nbx);
+    by = (int)((tu / (unsigned)nbx) % (unsigned)nby);
+    bz = (int)(tu / ((unsigned)nbx * (unsigned)nby));
 }
 
 template <typename T>
@@ -446,9 +447,8 @@ __device__ __forceinline__ void adj3d_prep_body(const AdjArgs<T> &a, long long b
     const long long ncell = (long long)g.n[0] * g.n[1] * g.n[2];
     const long long t = blk * kBlock + threadIdx.x;
     if (t >= ncell) return;
-    const int x = (int)(t % g.n[0]);
-    const int y = (int)((t / g.n[0]) % g.n[1]);
-    const int z = (int)(t / ((long long)g.n[0] * g.n[1]));
+    const unsigned tu = (unsigned)t, n0 = (unsigned)g.n[0], n1 = (unsigned)g.n[1];  // < 2^31 cells
+    const int x = (int)(tu % n0), y = (int)((tu / n0) % n1), z = (int)(tu / (n0 * n1));
     const long long idx = x + y * g.sy + z * g.sz;
     if (on_face(g, 0, x) || on_face(g, 1, y) || on_face(g, 2, z)) {
         a.Ps[idx] = T(0);

@@ -33,9 +33,8 @@ __global__ __launch_bounds__(kBlock) void k_init(const InitArgs<T> a) {
     const long long ncell = (long long)g.n[0] * g.n[1] * g.n[2];
     const long long t = blockIdx.x * (long long)kBlock + threadIdx.x;
     if (t >= ncell) return;
-    const int x = (int)(t % g.n[0]);
-    const int y = (int)((t / g.n[0]) % g.n[1]);
-    const int z = (int)(t / ((long long)g.n[0] * g.n[1]));
+    const unsigned tu = (unsigned)t, n0 = (unsigned)g.n[0], n1 = (unsigned)g.n[1];  // < 2^31 cells
+    const int x = (int)(tu % n0), y = (int)((tu / n0) % n1), z = (int)(tu / (n0 * n1));
     if (on_face(g, 0, x) || on_face(g, 1, y) || (g.dim == 3 && on_face(g, 2, z))) return;
     const long long idx = x + y * g.sy + z * g.sz;
     T v[4];
