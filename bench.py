@@ -70,10 +70,11 @@ def bytes_per_lup(cfg: dict) -> dict:
     """Algorithmic HBM bytes per lattice update of each stencil kernel (what it must move)."""
     e = 8 if cfg["precision"] == "F64" else 4
     D = cfg["dim"]
-    # 2D adjoint: one fused kernel (read lambda, u^{n-1}; write lambda).  3D adjoint: a pointwise
-    # kernel (read lambda, write (P*, V*)) then the marching kernel (read (P*, V*), u^{n-1}; write
-    # lambda); the timed "adj_step" covers both launches.
-    adj = (2 * (1 + D) + D) * e if D == 2 else (2 * (1 + D) + 2 * (1 + D) + D) * e
+    # adjoint: read lambda and u^{n-1}, write lambda.  The 3D adjoint runs as two launches (a
+    # pointwise kernel writes (P*, V*), the marching kernel reads them back); that intermediate is
+    # this implementation's cost, not the method's, so it is not counted.  The footprint box
+    # (kappa, u_S, kappa_bar) and the design grid are not counted either (under 2 B per update).
+    adj = (2 * (1 + D) + D) * e
     return {
         "fwd_step": (2 * (1 + D)) * e,          # read rho, u; write rho, u
         "adj_step": adj,
@@ -111,7 +112,7 @@ def read_traffic(kernel: str, wl: str, per_launch_alg: float):
 def cpu_baseline(wl: str, cfg: dict, gamma: np.ndarray) -> dict:
     """The FP64 oracle as it stands, on a bounded sample of the same workload."""
     from oracle import oracle as O
-    sample_steps = {"c1": 400, "c2": 40, "c3": 100, "c4": 1}[wl]
+    sample_steps = {"c1": 400, "c2": 40, "c3": 100, "c4": 3}[wl]
     c = dict(cfg)
     c["nsteps"] = sample_steps
     c["motion"] = cfg["motion"][: sample_steps + 1]
@@ -119,10 +120,6 @@ def cpu_baseline(wl: str, cfg: dict, gamma: np.ndarray) -> dict:
     if ob["kind"] != "NONE":
         ob["n1"] = min(ob["n1"], sample_steps)
     c["objective"] = ob
-    if wl == "c4":  # a 256^3 oracle step takes minutes: time it on a 128^3 copy of the workload
-        c = I.config_c4(n_side=128, nd_side=48, precision="F64", nsteps=2)
-        gamma = I.gamma_field(c["nd"], 3, 3)
-        sample_steps = 2
     grad = ob["kind"] != "NONE"
     t0 = time.perf_counter()
     O.solve(c, gamma, grad=grad)
@@ -157,6 +154,132 @@ def served_leg(n_req: int, rate: float, seed: int = 5) -> dict:
     return out
 
 
+# ---- rocprofv3 summaries (run on the CPU after a profiled run; they write profiles/) ----------
+# rocprofv3 kernel names of each timed kind, per dimension (3D adjoint: two launches per step)
+PROFILED = {("fwd_step", 2): ["k_fwd2d_batch"], ("fwd_step", 3): ["k_fwd3d_batch"],
+            ("adj_step", 2): ["k_adj2d_batch"],
+            ("adj_step", 3): ["k_adj3d_prep_batch", "k_adj3d_main_batch"]}
+
+
+def _csv(path):
+    import csv
+    return list(csv.DictReader(open(path)))
+
+
+def _json_line(path):
+    lines = [ln for ln in open(path) if ln.startswith("{")]
+    return json.loads(lines[-1]) if lines else {}
+
+
+def pmc_summary(fetch_csv: str, write_csv: str, wl: str, nsteps: int) -> None:
+    """HBM bytes per launch of fwd_step and adj_step from one FETCH_SIZE and one WRITE_SIZE pass
+    (each of a `--calibrate-copy` run), scaled by what the counters read for the 1 GiB copy."""
+    import collections
+    cfg, _ = workload(wl, nsteps)
+    cells = int(np.prod(cfg["n"]))
+    per = {}
+    for path, cn in ((fetch_csv, "FETCH_SIZE"), (write_csv, "WRITE_SIZE")):
+        agg = collections.defaultdict(list)
+        for r in _csv(path):
+            if r["Counter_Name"] == cn:
+                agg[(r["Kernel_Name"], r["Grid_Size"])].append(float(r["Counter_Value"]))
+        per[cn] = agg
+    gib_kib = 1024.0 * 1024.0
+    factor = {}
+    for cn, agg in per.items():
+        big = max((max(v) for (k, _), v in agg.items() if "copyBuffer" in k), default=0.0)
+        factor[cn] = gib_kib / big if big > 0 else float("nan")
+    bpl = bytes_per_lup(cfg)
+    for kind in ("fwd_step", "adj_step"):
+        names = PROFILED[(kind, cfg["dim"])]
+        kib = {}
+        desc = []
+        for cn, agg in per.items():
+            tot = 0.0
+            for nm in names:
+                # the launches of this kernel with the most common grid (the per-step launches)
+                cand = [(len(v), g, v) for (k, g), v in agg.items() if nm in k]
+                if not cand:
+                    break
+                n_l, grid, v = max(cand)
+                tot += sum(v) / len(v)
+                if cn == "FETCH_SIZE":
+                    desc.append(f"{nm}: {n_l} launches of grid {grid}")
+            else:
+                kib[cn] = tot
+        if len(kib) != 2:
+            continue
+        hbm = (kib["FETCH_SIZE"] * factor["FETCH_SIZE"] + kib["WRITE_SIZE"] * factor["WRITE_SIZE"]) * 1024
+        alg = bpl[kind] * cells
+        cmd = ("rocprofv3 --pmc {c} -d {d} -o {o} --output-format csv -- python3 bench.py "
+               f"--no-cpu-baseline --no-served --steps 1 --warmup 0 --workload {wl} "
+               f"--nsteps {nsteps} --calibrate-copy")
+        out = [f"# HBM traffic per launch of {kind} ({', '.join(names)}) for the {cfg['name']} workload",
+               "# commands (two passes, one counter each):"]
+        for path, cn in ((fetch_csv, "FETCH_SIZE"), (write_csv, "WRITE_SIZE")):
+            d = os.path.dirname(path)
+            o = os.path.basename(path).split("_counter_collection")[0]
+            out.append("#   " + cmd.format(c=cn, d=d, o=o))
+        out += ["# calibration: --calibrate-copy runs one 1 GiB device-to-device copy first; the counters "
+                "of that copy give",
+                f"#   fetch_factor = {factor['FETCH_SIZE']:.4f}, write_factor = {factor['WRITE_SIZE']:.4f} "
+                "(bytes moved / (counter KiB x 1024))",
+                "# launches averaged: " + "; ".join(desc),
+                f"# algorithmic bytes per launch: {bpl[kind]} B x {cells} cells = {alg}",
+                f"kernel = {kind}", f"workload = {wl}",
+                f"kernel_source_hash = {kernel_source_hash()}",
+                f"fetch_kib_per_launch = {kib['FETCH_SIZE']:.1f}",
+                f"write_kib_per_launch = {kib['WRITE_SIZE']:.1f}",
+                f"fetch_factor = {factor['FETCH_SIZE']:.4f}",
+                f"write_factor = {factor['WRITE_SIZE']:.4f}",
+                f"hbm_bytes_per_launch = {hbm:.0f}",
+                f"ratio_to_algorithmic = {hbm / alg:.3f}"]
+        path = os.path.join(ROOT, "profiles", f"traffic_{kind}_{wl}.txt")
+        open(path, "w").write("\n".join(out) + "\n")
+        print("\n".join(out))
+
+
+def trace_summary(prefix: str, log: str, plain_log: str, wl: str, cmd: str) -> None:
+    """Per-kernel durations of a `rocprofv3 --kernel-trace --stats` run, the per-step kernels split by
+    queue and grid, next to the bench lines of the profiled and of an unprofiled run."""
+    import collections
+    cfg, _ = workload(wl, 0)
+    stats = _csv(prefix + "_kernel_stats.csv")
+    out = [f"# rocprofv3 kernel trace: {cfg['name']} workload, {cfg['lattice']} "
+           f"{'x'.join(str(v) for v in cfg['n'][:cfg['dim']])}, {cfg['precision']}, "
+           f"{cfg['nsteps']} steps, checkpoint every {cfg['checkpoint_every']}",
+           f"# command: {cmd}",
+           f"# kernel sources: {kernel_source_hash()}   GPU: MI355X (gfx950), one device", "",
+           f"{'kernel':58s} {'calls':>7s} {'avg us':>8s} {'min us':>8s} {'max us':>8s} {'share %':>8s}"]
+    for r in stats[:12]:
+        name = r["Name"].replace('"', "").split("(")[0][:58]
+        out.append(f"{name:58s} {int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:8.2f} "
+                   f"{float(r['MinNs']) / 1e3:8.2f} {float(r['MaxNs']) / 1e3:8.2f} "
+                   f"{float(r['Percentage']):8.2f}")
+    agg = collections.defaultdict(list)
+    for r in _csv(prefix + "_kernel_trace.csv"):
+        k = r["Kernel_Name"]
+        if any(nm in k for v in PROFILED.values() for nm in v):
+            agg[(k.split("(")[0].replace("void ", ""), r["Queue_Id"], r["Grid_Size_X"])].append(
+                (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    out += ["", "per-step kernels by queue and grid (the lowest queue id carries the forward sweep and "
+                "the adjoint; the other one the segment recompute):"]
+    for (k, q, gsz), v in sorted(agg.items()):
+        if len(v) >= 4:
+            out.append(f"  {k:34s} queue {q:>2s} grid {gsz:>8s}: {len(v):6d} launches, "
+                       f"mean {sum(v) / len(v):8.2f} us")
+    keys = ("value", "ms_per_step", "kernels", "roofline")
+    prof, plain = _json_line(log), _json_line(plain_log) if plain_log else {}
+    out += ["", "bench.py line of the profiled run (live HIP-event timing on the library stream):",
+            "  " + json.dumps({k: prof.get(k) for k in keys})]
+    if plain:
+        out += ["bench.py line of the same workload without the profiler:",
+                "  " + json.dumps({k: plain.get(k) for k in keys})]
+    path = os.path.join(ROOT, "profiles", f"kernels_{cfg['lattice'].lower()}_{wl}.txt")
+    open(path, "w").write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -172,7 +295,18 @@ def main() -> int:
     ap.add_argument("--period", type=float, default=0.0, help="override the motion period")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 1 GiB device copy first (counter calibration)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic_*.txt from two rocprofv3 counter passes (CPU only)")
+    ap.add_argument("--trace-summary", nargs=3, metavar=("PREFIX", "LOG", "PLAIN_LOG"),
+                    help="write profiles/kernels_*.txt from a rocprofv3 kernel trace (CPU only)")
+    ap.add_argument("--trace-command", default="", help="the profiled command, for the summary")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary, args.workload, args.nsteps)
+        return 0
+    if args.trace_summary:
+        trace_summary(*args.trace_summary, args.workload, args.trace_command)
+        return 0
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the multi-GPU "
                                    "halo-exchange design is documented, not built)"}))
@@ -252,8 +386,11 @@ def main() -> int:
     K = cfg["checkpoint_every"] or N
     S = (N + K - 1) // K
     # forward-step launches: N in the forward sweep plus the recomputed segments (all but the last)
+    # (2D: the gather of each adjoint step rides in the next adjoint launch; only the last one
+    # is a launch of its own)
     launches = {"fwd_step": N + ((S - 1) * K if has_adj else 0),
-                "adj_step": N if has_adj else 0, "sens_gather": N if has_adj else 0}
+                "adj_step": N if has_adj else 0,
+                "sens_gather": (N if cfg["dim"] == 3 else 1) if has_adj else 0}
     tot = {k: launches[k] * timing[k]["mean_ms"] for k in launches}
     dom = max(tot, key=tot.get)
     bpl = bytes_per_lup(cfg)

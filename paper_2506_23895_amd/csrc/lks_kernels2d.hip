@@ -1,16 +1,20 @@
-// 2D D2Q9 kernels: one fused forward step and one fused adjoint step per launch.
+// 2D D2Q9 kernels: one fused forward step and one fused adjoint step per launch, both on wave
+// strips: the 64 lanes of a wave hold 64 consecutive columns and the wave walks a few rows, so
+// x-neighbours are one lane away (DPP row shifts) and y-neighbours are registers of the same lane.
 //
-// Forward step (Algorithm 1 body, Sec. 2.2-2.3), per 64x8 tile of output nodes:
-//   stage u (halo 2) and rho - 1 (halo 1) in LDS; evaluate the equilibrium E_i of every node of
-//   the tile plus a halo of 1 (strain from central differences, one-sided on non-periodic faces);
-//   pull rho* = sum_i E_i(x - c_i), m* = sum_i c_i E_i(x - c_i); transfer kappa and u_S at the node
-//   by a gather over the rotated design grid; implicit VPM update; composite boundary rules for the
-//   face nodes that copy from this node; FP64 objective partial; last-block reduction.
-// Adjoint step (the exact transpose, in reverse order), per 64x8 tile:
-//   lambda = Lambda + dj/dX on the tile plus halo 4; boundary transpose and force transpose give
-//   (P*, V*) on halo 3 and kappa_bar on the tile; the pull transpose E~_i(y) = P*(y+c_i) +
-//   c_i.V*(y+c_i) and its w-weighted moments (rho~, u~, s~) on halo 2; then Lambda^{n-1} from the
-//   transposed equilibrium and the transposed strain operator.
+// Forward step (Algorithm 1 body, Sec. 2.2-2.3): lanes 2..61 own output columns, the two lanes on
+// each side are the u halo.  Every row the wave needs (u with halo 2, rho - 1 with halo 1, kappa
+// and u_S of its output rows from the footprint store) is requested before any arithmetic; then,
+// row by row, the strain (central differences, one-sided on non-periodic faces) and the
+// equilibrium E_i, whose pulled parts land in three in-flight output rows; the VPM update, the
+// composite boundary rules of the face nodes that copy from this node, and one FP64 objective
+// partial per wave.  Extra blocks of the same launch transfer the next step onto its footprint box.
+// Adjoint step (the exact transpose, in reverse order): lanes 3..60 own output columns.  Per row,
+// lambda = Lambda + dj/dX, the boundary and force transposes give (P*, V*) and kappa_bar on the
+// footprint box; the w-weighted moments (rho~, u~, s~) of the pull transpose
+// E~_i(y) = P*(y+c_i) + c_i.V*(y+c_i) factor into an x-stencil (lane shifts) and a y-stencil
+// (registers); then Lambda^{n-1} from the transposed equilibrium and strain operator.  Extra blocks
+// of the same launch run the sensitivity gather of the step after it.
 // rho is carried as rho - 1 on the GPU: the constant part adds exactly 1 to rho* and nothing to
 // m* (sum_i w_i = 1, sum_i w_i c_i = 0), so the update is unchanged and FP32 keeps the fluctuation.
 #include "lks_device.hpp"
