@@ -205,7 +205,8 @@ int plan(const lks_desc *d, Layout &L, std::string *err) {
     L.b_traj = L.fwd_only ? 0 : (size_t)L.banks * (L.K + 1) * D * L.F * e;
     L.b_box = L.fwd_only ? 0 : (size_t)L.banks * L.K * nf * L.box.cells * e;
     L.b_xring = 2 * nf * L.box.cells * e;  // kappa, u_S of the steps outside the stored segment
-    L.b_kbar = L.fwd_only ? 0 : (size_t)2 * L.box.cells * e;  // kappa_bar of steps n (n even / odd)
+    // kappa_bar of steps n (n even / odd), padded so the gather's 5 x 5 tap windows stay in bounds
+    L.b_kbar = L.fwd_only ? 0 : (size_t)(2 * L.box.cells + 4 * L.box.bsy + 8) * e;
     L.b_adj = L.fwd_only ? 0 : 2 * nf * L.F * e;
     L.b_final = nf * L.F * e;
     L.b_design = (size_t)L.nd * (3 * e + 2 * 8);  // gamma, kref, sens out; kprime, G

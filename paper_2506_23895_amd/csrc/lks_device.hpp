@@ -360,10 +360,58 @@ __device__ __forceinline__ void store_partial(const ObjParams &o, double v, long
     if (threadIdx.x == 0) o.partials[blin] = bs;
 }
 
+// Blocks of a launch are dispatched round-robin over the 8 XCDs, each with its own L2.  Tile of
+// the t-th dispatched block out of T: XCD t % 8 gets a contiguous run of tiles (row-major), so
+// row chunks that share halo rows run on the same XCD close in time and the halos hit its L2.
+// Odd XCDs walk their run backwards, so the last run (the bottom face rows, slower code) starts
+// early instead of forming the tail of the launch.
+__device__ __forceinline__ long long xcd_tile(long long t, long long T) {
+    const long long q = T >> 3, r = T & 7, x = t & 7, l = t >> 3;
+    const long long n = q + (x < r ? 1 : 0);
+    return x * q + (x < r ? x : r) + ((x & 1) ? n - 1 - l : l);
+}
+
 // ---- sensitivity gather (one thread per design node) ------------------------------------------
 // G(xi) += sum_x W(x - x_ref(xi)) kappa_bar(x) over the step's footprint box: the weight is a
 // product over analysis axes and the support spans at most 2s + 1 nodes per axis, so per-axis
 // weights are formed first and every load of a z-plane is issued together.
+// Taps of an MW x MW window per z-plane: the weight is a product over analysis axes, so per-axis
+// weights are formed first.  The window's origin is clamped into the step's box and the kappa_bar
+// allocation is padded by 4 box rows + 8 nodes, so every tap address is in bounds and every load
+// of a plane is issued unconditionally (one 64-bit address per row, columns as immediate offsets);
+// taps outside [lo, hi] have weight 0 and are dropped by selection, never multiplied.
+template <typename T, int MW>
+__device__ __forceinline__ double sens_window(const SensArgs<T> &a, const int lo[3], const int hi[3],
+                                              const double xr[3]) {
+    T wx[MW], wy[MW];
+#pragma unroll
+    for (int t = 0; t < MW; ++t) {
+        wx[t] = lo[0] + t <= hi[0] ? wk<T>(a.des.weight, (T)(lo[0] + t - xr[0])) : T(0);
+        wy[t] = lo[1] + t <= hi[1] ? wk<T>(a.des.weight, (T)(lo[1] + t - xr[1])) : T(0);
+    }
+    const LKS_GLOBAL T *__restrict__ kb = gld(a.kbar);
+    const int ox = min(lo[0], a.m.hi[0]), oy = min(lo[1], a.m.hi[1]);
+    const long long bsy = a.box.bsy;
+    double acc = 0.0;
+    for (int z = lo[2]; z <= hi[2]; ++z) {
+        const T wz = (a.dim == 3) ? wk<T>(a.des.weight, (T)(z - xr[2])) : T(1);
+        if (wz == T(0)) continue;
+        const LKS_GLOBAL T *r0 = kb + box_index(a.box, a.m, a.dim, ox, oy, z);
+        T kv[MW][MW];
+#pragma unroll
+        for (int ty = 0; ty < MW; ++ty)
+#pragma unroll
+            for (int tx = 0; tx < MW; ++tx) kv[ty][tx] = r0[ty * bsy + tx];
+#pragma unroll
+        for (int ty = 0; ty < MW; ++ty)
+#pragma unroll
+            for (int tx = 0; tx < MW; ++tx)
+                if (wx[tx] != T(0) && wy[ty] != T(0))
+                    acc += (double)(wx[tx] * wy[ty] * wz) * (double)kv[ty][tx];
+    }
+    return acc;
+}
+
 template <typename T>
 __device__ __forceinline__ void sens_body(const SensArgs<T> &a, long long blk) {
     const long long ndn = (long long)a.des.nd[0] * a.des.nd[1] * a.des.nd[2];
@@ -383,34 +431,8 @@ __device__ __forceinline__ void sens_body(const SensArgs<T> &a, long long blk) {
         lo[r] = max(a.m.lo[r], (int)ceil(xr[r] - s));
         hi[r] = min(a.m.hi[r], (int)floor(xr[r] + s));
     }
-    // the weight is a product over analysis axes and the support spans at most 2s + 1 nodes per
-    // axis: per-axis weights first, then every load of a z-plane issued together
-    constexpr int MW = 5;
-    T wx[MW], wy[MW];
-#pragma unroll
-    for (int t = 0; t < MW; ++t) {
-        wx[t] = lo[0] + t <= hi[0] ? wk<T>(a.des.weight, (T)(lo[0] + t - xr[0])) : T(0);
-        wy[t] = lo[1] + t <= hi[1] ? wk<T>(a.des.weight, (T)(lo[1] + t - xr[1])) : T(0);
-    }
-    double acc = 0.0;
-    for (int z = lo[2]; z <= hi[2]; ++z) {
-        const T wz = (a.dim == 3) ? wk<T>(a.des.weight, (T)(z - xr[2])) : T(1);
-        if (wz == T(0)) continue;
-        T kv[MW][MW];
-#pragma unroll
-        for (int ty = 0; ty < MW; ++ty)
-#pragma unroll
-            for (int tx = 0; tx < MW; ++tx)
-                kv[ty][tx] = (wx[tx] != T(0) && wy[ty] != T(0))
-                                 ? a.kbar[box_index(a.box, a.m, a.dim, lo[0] + tx, lo[1] + ty, z)]
-                                 : T(0);
-#pragma unroll
-        for (int ty = 0; ty < MW; ++ty)
-#pragma unroll
-            for (int tx = 0; tx < MW; ++tx)
-                if (wx[tx] != T(0) && wy[ty] != T(0))
-                    acc += (double)(wx[tx] * wy[ty] * wz) * (double)kv[ty][tx];
-    }
+    // LIN support: at most 3 nodes per axis; COS4: at most 5 (weight kind is uniform per job)
+    const double acc = a.des.weight == 1 ? sens_window<T, 3>(a, lo, hi, xr) : sens_window<T, 5>(a, lo, hi, xr);
     a.G[i] += acc;
 }
 

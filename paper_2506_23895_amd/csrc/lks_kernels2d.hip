@@ -300,17 +300,6 @@ __host__ __device__ inline int fwd2d_grid_x(const Geom &g) {
 }
 __host__ __device__ inline int fwd2d_grid_y(const Geom &g) { return (g.n[1] + RY - 1) / RY; }
 
-// Blocks of a launch are dispatched round-robin over the 8 XCDs, each with its own L2.  Tile of
-// the t-th dispatched block out of T: XCD t % 8 gets a contiguous run of tiles (row-major), so
-// row chunks that share halo rows run on the same XCD close in time and the halos hit its L2.
-// Odd XCDs walk their run backwards, so the last run (the bottom face rows, slower code) starts
-// early instead of forming the tail of the launch.
-__device__ __forceinline__ long long xcd_tile(long long t, long long T) {
-    const long long q = T >> 3, r = T & 7, x = t & 7, l = t >> 3;
-    const long long n = q + (x < r ? 1 : 0);
-    return x * q + (x < r ? x : r) + ((x & 1) ? n - 1 - l : l);
-}
-
 // Row chunk of the r-th dispatched chunk row out of gy: alternately from both ends, so the waves
 // that touch the y faces (slower code) start early instead of forming the tail of the launch.
 __device__ __forceinline__ int chunk_row(int r, int gy) { return (r & 1) ? gy - 1 - (r >> 1) : (r >> 1); }
@@ -665,6 +654,7 @@ __global__ __launch_bounds__(kBlock, LKS_ADJ2D_WAVES) void k_adj2d_batch(const A
         sens_body<T>(*a.sens, t - na);
         return;
     }
+    // (XCD banding as in the forward measured slower here: 26.9 vs 25.8 us at 1024^2)
     adj2d_body<T>(a, (int)((unsigned)t % (unsigned)nbx), chunk_row((int)((unsigned)t / (unsigned)nbx), adj2d_grid_y(a.g)));
 }
 

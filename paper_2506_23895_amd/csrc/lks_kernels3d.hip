@@ -379,11 +379,20 @@ __device__ __forceinline__ int job_of3(const long long *tile0, int njobs, long l
     return lo;
 }
 
+#ifndef LKS_XCD3D
+#define LKS_XCD3D 1
+#endif
+// column (bx, by) and z chunk bz of the t-th dispatched block: each XCD takes a contiguous run of
+// tiles (x fastest), so blocks that share x-y halo planes read them through one L2
 template <typename T>
 __device__ __forceinline__ void tile_coords3(const Geom &g, long long t, int &bx, int &by, int &bz) {
     const int nbx = (g.n[0] + Tile3<T>::TX - 1) / Tile3<T>::TX;
     const int nby = (g.n[1] + Tile3<T>::TY - 1) / Tile3<T>::TY;
+#if LKS_XCD3D
+    const unsigned tu = (unsigned)xcd_tile(t, (long long)nbx * nby * ((g.n[2] + Tile3<T>::ZC - 1) / Tile3<T>::ZC));
+#else
     const unsigned tu = (unsigned)t;
+#endif
     bx = (int)(tu % (unsigned)nbx);
     by = (int)((tu / (unsigned)nbx) % (unsigned)nby);
     bz = (int)(tu / ((unsigned)nbx * (unsigned)nby));
