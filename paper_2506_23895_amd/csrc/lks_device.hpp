@@ -151,6 +151,14 @@ __device__ __forceinline__ long long box_index(const BoxGeom &b, const StepMotio
            (dim == 3 ? (long long)(z - m.lo[2]) * b.bsz : 0LL);
 }
 
+// 2D box index of (x, y) clamped into the step's box: always a valid element, so a load from it
+// needs no per-lane branch (the caller selects zero where the node is outside).  Boxes hold fewer
+// than 2^31 nodes, so 32-bit arithmetic suffices.
+__device__ __forceinline__ int box_index2_clamped(const BoxGeom &b, const StepMotion &m, int x, int y) {
+    const int cx = min(max(x, m.lo[0]), m.hi[0]), cy = min(max(y, m.lo[1]), m.hi[1]);
+    return (cx - m.lo[0]) + (cy - m.lo[1]) * (int)b.bsy;
+}
+
 // Transfer of one step onto its footprint box, one thread per box cell: writes kappa and u_S
 // into box arrays (fixed extent bn, this step's origin m.lo).  Launched as extra blocks of the
 // previous step's stencil launch, so it runs off the stencil's critical path.

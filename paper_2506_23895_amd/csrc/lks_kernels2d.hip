@@ -121,19 +121,6 @@ __device__ __forceinline__ void fwd2d_rows(const FwdArgs<T> &a, int strip, int y
     T ux[RY + 5], uy[RY + 5], rv[RY + 2];
     T kb[RY], sbx[RY], sby[RY];  // kappa, u_S of the output rows (footprint waves only)
 #pragma unroll
-    for (int k = 0; k < RY; ++k) {
-        kb[k] = sbx[k] = sby[k] = T(0);
-        if (wbox) {  // wave-uniform; unconditional loads from a clamped index, then select
-            const int o = y0 + k;
-            const bool inb = c >= a.m.lo[0] && c <= a.m.hi[0] && o >= a.m.lo[1] && o <= a.m.hi[1];
-            const long long bi = inb ? box_index(a.box, a.m, 2, c, o, 0) : 0;
-            const T k0 = gld(a.kin)[bi], s0 = gld(a.usin[0])[bi], s1 = gld(a.usin[1])[bi];
-            kb[k] = inb ? k0 : T(0);
-            sbx[k] = inb ? s0 : T(0);
-            sby[k] = inb ? s1 : T(0);
-        }
-    }
-#pragma unroll
     for (int k = 0; k < RY + 5; ++k) {
         int yw = y0 - 3 + k;
         ux[k] = uy[k] = T(0);
@@ -160,6 +147,29 @@ __device__ __forceinline__ void fwd2d_rows(const FwdArgs<T> &a, int strip, int y
             const bool ok = cin && wrapc(yw, ny, g.per[1]);
             const T v = r_in[ok ? cw + (long long)yw * g.sy : 0];
             rv[k] = ok ? v : T(0);
+        }
+    }
+
+    // kappa, u_S last, in one block: every index comes from clamped coordinates (no per-lane
+    // branch), all loads are issued before the first select, and the field rows above are already
+    // in flight while they wait
+#pragma unroll
+    for (int k = 0; k < RY; ++k) kb[k] = sbx[k] = sby[k] = T(0);
+    if (wbox) {  // wave-uniform
+        T k0[RY], s0[RY], s1[RY];
+#pragma unroll
+        for (int k = 0; k < RY; ++k) {
+            const int bi = box_index2_clamped(a.box, a.m, c, y0 + k);
+            k0[k] = gld(a.kin)[bi];
+            s0[k] = gld(a.usin[0])[bi];
+            s1[k] = gld(a.usin[1])[bi];
+        }
+#pragma unroll
+        for (int k = 0; k < RY; ++k) {
+            const bool inb = in_box(a.m, 2, c, y0 + k, 0);
+            kb[k] = inb ? k0[k] : T(0);
+            sbx[k] = inb ? s0[k] : T(0);
+            sby[k] = inb ? s1[k] : T(0);
         }
     }
 
@@ -419,19 +429,6 @@ __device__ __forceinline__ void adj2d_rows(const AdjArgs<T> &a, int strip, int y
         ly[k] = lv[k] ? v1 : T(0);
         kk[k] = ksx[k] = ksy[k] = T(0);
     }
-    if (wbox) {  // wave-uniform
-#pragma unroll
-        for (int k = 0; k < NL; ++k) {
-            int rw = yl0 + k;
-            if (!IN) wrapc(rw, ny, g.per[1]);
-            const bool inb = lv[k] && in_box(a.m, 2, cw, rw, 0);
-            const long long bi = inb ? box_index(a.box, a.m, 2, cw, rw, 0) : 0;
-            const T k0 = gld(a.kbox)[bi], s0 = gld(a.usbox[0])[bi], s1 = gld(a.usbox[1])[bi];
-            kk[k] = inb ? k0 : T(0);
-            ksx[k] = inb ? s0 : T(0);
-            ksy[k] = inb ? s1 : T(0);
-        }
-    }
     // velocities the outputs and kappa_bar need, requested with the lambda rows
     const bool out_lane = lane >= 3 && lane <= 60 && c < nx;
     T upx[NR], upy[NR], ucx[NR], ucy[NR];
@@ -444,12 +441,43 @@ __device__ __forceinline__ void adj2d_rows(const AdjArgs<T> &a, int strip, int y
         upx[ko] = ok ? p0 : T(0);
         upy[ko] = ok ? p1 : T(0);
         ucx[ko] = ucy[ko] = T(0);
-        if (wbox) {  // wave-uniform
-            const bool okb = ok && in_box(a.m, 2, c, o, 0);
-            const long long ib = okb ? idx : 0;
-            const T c0 = gld(a.ucur[0])[ib], c1 = gld(a.ucur[1])[ib];
-            ucx[ko] = okb ? c0 : T(0);
-            ucy[ko] = okb ? c1 : T(0);
+    }
+    // kappa, u_S and u^n on the footprint, in one block after the rows above: indices from
+    // clamped coordinates (no per-lane branch), every load issued before the first select
+    if (wbox) {  // wave-uniform
+        T k0[NL], s0[NL], s1[NL], c0[NR], c1[NR];
+        int rws[NL];
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            int rw = yl0 + k;
+            if (!IN) wrapc(rw, ny, g.per[1]);
+            rws[k] = rw;
+            const int bi = box_index2_clamped(a.box, a.m, cw, rw);
+            k0[k] = gld(a.kbox)[bi];
+            s0[k] = gld(a.usbox[0])[bi];
+            s1[k] = gld(a.usbox[1])[bi];
+        }
+#pragma unroll
+        for (int ko = 0; ko < NR; ++ko) {
+            const int o = min(y0 + ko, ny - 1);
+            const int cx = min(max(c, a.m.lo[0]), a.m.hi[0]), oy = min(max(o, a.m.lo[1]), a.m.hi[1]);
+            const long long ib = cx + (long long)oy * g.sy;  // a node of the box: inside the grid
+            c0[ko] = gld(a.ucur[0])[ib];
+            c1[ko] = gld(a.ucur[1])[ib];
+        }
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const bool inb = lv[k] && in_box(a.m, 2, cw, rws[k], 0);
+            kk[k] = inb ? k0[k] : T(0);
+            ksx[k] = inb ? s0[k] : T(0);
+            ksy[k] = inb ? s1[k] : T(0);
+        }
+#pragma unroll
+        for (int ko = 0; ko < NR; ++ko) {
+            const int o = y0 + ko;
+            const bool okb = out_lane && o < ny && in_box(a.m, 2, c, o, 0);
+            ucx[ko] = okb ? c0[ko] : T(0);
+            ucy[ko] = okb ? c1[ko] : T(0);
         }
     }
     if (obj_on && (wbox || !kobj)) {  // kappa objectives are non-zero on the footprint only
