@@ -276,9 +276,15 @@ __device__ __forceinline__ void fwd2d_rows(const FwdArgs<T> &a, int strip, int y
         tlm[0] = tlm[1]; tlm[1] = tlm[2]; tlm[2] = T(0);
     }
     if (obj_on) {
+        // objectives weighted by kappa vanish off the footprint: a wave that does not meet it
+        // stores its exact sum, +0, without the cross-lane reduction
+        if (!wbox && obj_uses_kappa(a.obj.kind)) {
+            if (lane == 0) gst(a.obj.partials)[pslot] = 0.0;
+        } else {
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) jacc += __shfl_xor(jacc, o, 64);
-        if (lane == 0) gst(a.obj.partials)[pslot] = jacc;
+            for (int o = 32; o > 0; o >>= 1) jacc += __shfl_xor(jacc, o, 64);
+            if (lane == 0) gst(a.obj.partials)[pslot] = jacc;
+        }
     }
 }
 
