@@ -68,6 +68,17 @@ def test_ledger_sizes_and_budget():
     assert lks.query_bytes(c3, hbm_budget=1 << 20) == b
 
 
+def test_grids_of_2_pow_31_nodes_rejected():
+    # the kernels decompose node indices with 32-bit arithmetic: create refuses larger grids
+    # (checked before any allocation, so this runs without a GPU)
+    cfg = I.config_c4(n_side=16, nd_side=6, nsteps=2)
+    cfg["n"] = (2048, 1024, 1024)  # 2^31 nodes
+    with pytest.raises(lks.LksError) as e:
+        lks.query_bytes(cfg)
+    assert e.value.code == lks.LKS_EINVAL
+    assert "2^31" in str(e.value)
+
+
 def test_create_rejects_over_budget_without_gpu():
     with pytest.raises(lks.LksError) as e:
         lks.Solver(I.config_c3(), hbm_budget=1 << 20)
