@@ -545,7 +545,7 @@ int launch_adj_dev(lks_ctx *c, const lks::AdjArgs<T> *dargs, const lks::SensArgs
                 ? lks::launch_adj2d_batch<T>(dargs, c->tile0, 1, lks::tiles2d(c->L.g), c->stream)
                 : lks::launch_adj3d_batch<T>(dargs, c->tile0, (c->L.ncell + lks::kBlockHost - 1) / lks::kBlockHost,
                                              c->tile0, lks::tiles3d(c->L.g, (int)c->L.esz), 1,
-                                             c->d.lattice, c->stream);
+                                             c->d.lattice, c->L.g.per[2] != 0, c->stream);
     }
     HIPCHK(c, e);
     {
@@ -1219,6 +1219,7 @@ int round_impl(lks_batch *b, lks_ctx *const *cs, int n, int *done) {
         int kind, li;
         long long args, t0, t1, total, total1;
         int njobs;
+        bool pz = false;  // 3D adjoint: every job periodic in z
     };
     std::vector<Launch> ls;
     for (int li = 0; li < 3; ++li) {
@@ -1245,6 +1246,8 @@ int round_impl(lks_batch *b, lks_ctx *const *cs, int n, int *done) {
             Launch L{1, li, put(R.adj[li].data(), R.adj[li].size() * sizeof(lks::AdjArgs<T>)),
                      put(p.data(), p.size() * 8), put(q.data(), q.size() * 8), tot, totb,
                      (int)R.adj[li].size()};
+            L.pz = true;
+            for (const auto &aj : R.adj[li]) L.pz = L.pz && aj.g.per[2] != 0;
             ls.push_back(L);
         }
     }
@@ -1279,7 +1282,8 @@ int round_impl(lks_batch *b, lks_ctx *const *cs, int n, int *done) {
             const auto *a = reinterpret_cast<const lks::AdjArgs<T> *>(dv + L.args);
             e = L.li == 0 ? lks::launch_adj2d_batch<T>(a, t0, L.njobs, L.total, b->stream)
                           : lks::launch_adj3d_batch<T>(a, reinterpret_cast<const long long *>(dv + L.t1), L.total1,
-                                                       t0, L.total, L.njobs, L.li == 1 ? LKS_D3Q19 : LKS_D3Q15, b->stream);
+                                                       t0, L.total, L.njobs, L.li == 1 ? LKS_D3Q19 : LKS_D3Q15, L.pz,
+                                                       b->stream);
         }
         if (e != hipSuccess) {
             b->err = hipGetErrorString(e);

@@ -530,16 +530,42 @@ __device__ __forceinline__ T deriv_T3(const T f[5], int c, int n, int per) {
     return acc;
 }
 
-template <typename T, int Q>
-__device__ __forceinline__ void adj3d_main_body(const AdjArgs<T> &a, int bx, int by, int bz) {
-    constexpr int TX = Tile3<T>::TX, TY = Tile3<T>::TY, ZC = Tile3<T>::ZC, NT = TX * TY;
-    constexpr int PX = TX + 6, PY = TY + 6, PP = PX * PY;  // (P*, V*) plane, halo 3
-    constexpr int MX = TX + 4, MY = TY + 4, MP = MX * MY;  // moment plane, halo 2
+// LDS of the z-marching adjoint: three (P*, V*) planes with halo 3, then the ring of s~ planes
+// (halo 2).  A domain that is not periodic in z keeps five planes of all six s~ components (the
+// transposed one-sided rows at the z faces read two planes each way; outputs lag the moments by
+// two planes).  A z-periodic domain needs only the central difference along z: outputs lag by
+// one plane, s~ xz, yz, zz keep three planes and s~ xx, yy, xy two, which lets three blocks share
+// a CU instead of two.
+template <typename T>
+struct Adj3Lds {
+    static constexpr int TX = Tile3<T>::TX, TY = Tile3<T>::TY;
+    static constexpr int PX = TX + 6, PY = TY + 6, PP = PX * PY;  // (P*, V*) plane, halo 3
+    static constexpr int MX = TX + 4, MY = TY + 4, MP = MX * MY;  // moment plane, halo 2
+    static constexpr int SPV = 3 * 4 * PP;
+    static constexpr size_t bytes(bool pz) { return (size_t)(SPV + (pz ? 15 : 30) * MP) * sizeof(T); }
+};
+
+// s~ component c (xx, yy, zz, xy, xz, yz) of moment plane z in the ring
+template <typename T, bool PZ>
+__device__ __forceinline__ T *s_plane(T *ss, int c, int z) {
+    constexpr int MP = Adj3Lds<T>::MP;
+    if (!PZ) return ss + (ring5(z) * 6 + c) * MP;
+    // z-derivative components (zz, xz, yz: 2, 4, 5) in three planes, the others in two
+    if (c == 2 || c == 4 || c == 5) return ss + (ring3(z) * 3 + (c == 2 ? 0 : c - 3)) * MP;
+    return ss + (9 + (z & 1) * 3 + (c == 3 ? 2 : c)) * MP;
+}
+
+template <typename T, int Q, bool PZ>
+__device__ __forceinline__ void adj3d_main_body(const AdjArgs<T> &a, int bx, int by, int bz, T *lds) {
+    using L = Adj3Lds<T>;
+    constexpr int TX = L::TX, TY = L::TY, ZC = Tile3<T>::ZC, NT = TX * TY;
+    constexpr int PX = L::PX, PP = L::PP, MX = L::MX, MP = L::MP;
     constexpr int NP = (PP + NT - 1) / NT;
-    constexpr int NH = MP - NT;                            // halo moment nodes
+    constexpr int NH = MP - NT;  // halo moment nodes
+    constexpr int LAG = PZ ? 1 : 2;  // output plane = moment plane - LAG
     static_assert(NH <= NT, "one halo pass");
-    __shared__ T spv[3][4][PP];
-    __shared__ T ss[5][6][MP];  // s~ xx, yy, zz, xy, xz, yz
+    T(*spv)[4][PP] = reinterpret_cast<T(*)[4][PP]>(lds);
+    T *ss = lds + L::SPV;
 
     const Geom &g = a.g;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
@@ -601,7 +627,8 @@ __device__ __forceinline__ void adj3d_main_body(const AdjArgs<T> &a, int bx, int
         }
     };
 
-    for (int zp = zs - 3; zp <= zs - 1; ++zp) {
+    const int zfirst = zs - LAG;  // first moment plane
+    for (int zp = zfirst - 1; zp <= zfirst + 1; ++zp) {
         fetch_pv(zp);
         commit_pv(zp);
     }
@@ -611,11 +638,10 @@ __device__ __forceinline__ void adj3d_main_body(const AdjArgs<T> &a, int bx, int
     for (int t = 0; t < 3; ++t) ru[t][0] = ru[t][1] = ru[t][2] = ru[t][3] = T(0);
     const T A2 = T(2) * a.A;
 
-    for (int zm = zs - 2; zm <= ze + 1; ++zm) {
+    for (int zm = zfirst; zm <= ze - 1 + LAG; ++zm) {
         fetch_pv(zm + 2);  // in flight during the moment pass
         int zw = zm;
         const bool zin = wrapc(zw, nz, g.per[2]);
-        const int sm = ring5(zm);
         {   // own column first, then one pass over the halo ring
             T m[10];
             const int lx = ox + 2, ly = oy + 2;
@@ -624,7 +650,7 @@ __device__ __forceinline__ void adj3d_main_body(const AdjArgs<T> &a, int bx, int
 #pragma unroll
                 for (int c = 0; c < 10; ++c) m[c] = T(0);
 #pragma unroll
-            for (int c = 0; c < 6; ++c) ss[sm][c][ly * MX + lx] = m[4 + c];
+            for (int c = 0; c < 6; ++c) s_plane<T, PZ>(ss, c, zm)[ly * MX + lx] = m[4 + c];
             ru[2][0] = m[0];
             ru[2][1] = m[1];
             ru[2][2] = m[2];
@@ -649,21 +675,21 @@ __device__ __forceinline__ void adj3d_main_body(const AdjArgs<T> &a, int bx, int
 #pragma unroll
                     for (int c = 0; c < 10; ++c) m[c] = T(0);
 #pragma unroll
-                for (int c = 0; c < 6; ++c) ss[sm][c][hy * MX + hx] = m[4 + c];
+                for (int c = 0; c < 6; ++c) s_plane<T, PZ>(ss, c, zm)[hy * MX + hx] = m[4 + c];
             }
         }
         __syncthreads();
         commit_pv(zm + 2);  // replaces plane zm - 1, no longer read
-        const int zo = zm - 2;
+        const int zo = zm - LAG;
         const int gx = x0 + ox, gy = y0 + oy;
         if (zo >= zs && zo < ze && gx < nx && gy < ny) {
             const long long idx = gx + gy * g.sy + zo * g.sz;
             const int c0 = (oy + 2) * MX + (ox + 2);
-            const int so = ring5(zo);
-            const T rt = ru[0][0];
-            const T ut[3] = {ru[0][1], ru[0][2], ru[0][3]};
-            const T sxx = ss[so][0][c0], syy = ss[so][1][c0], szz = ss[so][2][c0];
-            const T sxy = ss[so][3][c0], sxz = ss[so][4][c0], syz = ss[so][5][c0];
+            const T rt = ru[2 - LAG][0];
+            const T ut[3] = {ru[2 - LAG][1], ru[2 - LAG][2], ru[2 - LAG][3]};
+            const T sxx = s_plane<T, PZ>(ss, 0, zo)[c0], syy = s_plane<T, PZ>(ss, 1, zo)[c0];
+            const T szz = s_plane<T, PZ>(ss, 2, zo)[c0], sxy = s_plane<T, PZ>(ss, 3, zo)[c0];
+            const T sxz = s_plane<T, PZ>(ss, 4, zo)[c0], syz = s_plane<T, PZ>(ss, 5, zo)[c0];
             const T u[3] = {a.uprev[0][idx], a.uprev[1][idx], a.uprev[2][idx]};
             T v[3];
             v[0] = T(3) * ut[0] + T(9) * (sxx * u[0] + sxy * u[1] + sxz * u[2]) - T(3) * rt * u[0];
@@ -675,14 +701,21 @@ __device__ __forceinline__ void adj3d_main_body(const AdjArgs<T> &a, int bx, int
             for (int aa = 0; aa < 3; ++aa) {
                 T f[5];
                 const int cx_ = sidx[aa][0], cy_ = sidx[aa][1], cz_ = sidx[aa][2];
+                const T *px = s_plane<T, PZ>(ss, cx_, zo), *py = s_plane<T, PZ>(ss, cy_, zo);
 #pragma unroll
-                for (int o = 0; o < 5; ++o) f[o] = ss[so][cx_][c0 + o - 2];
+                for (int o = 0; o < 5; ++o) f[o] = px[c0 + o - 2];
                 v[aa] += A2 * deriv_T3(f, gx, nx, g.per[0]);
 #pragma unroll
-                for (int o = 0; o < 5; ++o) f[o] = ss[so][cy_][c0 + (o - 2) * MX];
+                for (int o = 0; o < 5; ++o) f[o] = py[c0 + (o - 2) * MX];
                 v[aa] += A2 * deriv_T3(f, gy, ny, g.per[1]);
+                if (PZ) {  // periodic z: the central difference reads planes zo - 1 and zo + 1 only
+                    f[0] = f[2] = f[4] = T(0);
+                    f[1] = s_plane<T, PZ>(ss, cz_, zo - 1)[c0];
+                    f[3] = s_plane<T, PZ>(ss, cz_, zo + 1)[c0];
+                } else {
 #pragma unroll
-                for (int o = 0; o < 5; ++o) f[o] = ss[ring5(zo + o - 2)][cz_][c0];
+                    for (int o = 0; o < 5; ++o) f[o] = s_plane<T, PZ>(ss, cz_, zo + o - 2)[c0];
+                }
                 v[aa] += A2 * deriv_T3(f, zo, nz, g.per[2]);
             }
             a.Pout[idx] = rt;
@@ -699,16 +732,20 @@ __device__ __forceinline__ void adj3d_main_body(const AdjArgs<T> &a, int bx, int
     }
 }
 
+// pz: every job of the launch is periodic in z (the smaller LDS layout; dynamic LDS sized to it)
 template <typename T, int Q>
 __global__ __launch_bounds__(Tile3<T>::TX * Tile3<T>::TY) void k_adj3d_main_batch(const AdjArgs<T> *__restrict__ args,
                                                                                  const long long *__restrict__ tile0,
-                                                                                 int njobs) {
+                                                                                 int njobs, int pz) {
+    extern __shared__ __align__(16) unsigned char adj3_lds[];
     const long long b = blockIdx.x;
     const int j = __builtin_amdgcn_readfirstlane(job_of3(tile0, njobs, b));
     const AdjArgs<T> &a = args[j];
     int bx, by, bz;
     tile_coords3<T>(a.g, njobs == 1 ? b : b - tile0[j], bx, by, bz);
-    adj3d_main_body<T, Q>(a, bx, by, bz);
+    T *lds = reinterpret_cast<T *>(adj3_lds);
+    if (pz) adj3d_main_body<T, Q, true>(a, bx, by, bz, lds);
+    else adj3d_main_body<T, Q, false>(a, bx, by, bz, lds);
 }
 
 long long fwd_blocks3d(const Geom &g, int lattice, int esz) {
@@ -738,13 +775,16 @@ hipError_t launch_fwd3d_batch(const FwdArgs<T> *args, const long long *tile0, in
 
 template <typename T>
 hipError_t launch_adj3d_batch(const AdjArgs<T> *args, const long long *blk0, long long nblk,
-                              const long long *tile0, long long ntiles, int njobs, int lattice,
+                              const long long *tile0, long long ntiles, int njobs, int lattice, bool pz,
                               hipStream_t s) {
     if (njobs == 0) return hipSuccess;
     hipLaunchKernelGGL(k_adj3d_prep_batch<T>, dim3((unsigned)nblk), dim3(kBlock), 0, s, args, blk0, njobs);
     const dim3 blk(Tile3<T>::TX * Tile3<T>::TY);
-    if (lattice == 2) hipLaunchKernelGGL((k_adj3d_main_batch<T, 19>), dim3((unsigned)ntiles), blk, 0, s, args, tile0, njobs);
-    else hipLaunchKernelGGL((k_adj3d_main_batch<T, 15>), dim3((unsigned)ntiles), blk, 0, s, args, tile0, njobs);
+    const unsigned lds = (unsigned)Adj3Lds<T>::bytes(pz);
+    if (lattice == 2)
+        hipLaunchKernelGGL((k_adj3d_main_batch<T, 19>), dim3((unsigned)ntiles), blk, lds, s, args, tile0, njobs, (int)pz);
+    else
+        hipLaunchKernelGGL((k_adj3d_main_batch<T, 15>), dim3((unsigned)ntiles), blk, lds, s, args, tile0, njobs, (int)pz);
     return hipGetLastError();
 }
 
@@ -752,7 +792,7 @@ hipError_t launch_adj3d_batch(const AdjArgs<T> *args, const long long *blk0, lon
     template hipError_t launch_fwd3d_batch<T>(const FwdArgs<T> *, const long long *, int, long long,  \
                                               int, hipStream_t);                                      \
     template hipError_t launch_adj3d_batch<T>(const AdjArgs<T> *, const long long *, long long,       \
-                                              const long long *, long long, int, int, hipStream_t);
+                                              const long long *, long long, int, int, bool, hipStream_t);
 LKS_INST3(float)
 LKS_INST3(double)
 #undef LKS_INST3
