@@ -488,7 +488,7 @@ long long fwd_tiles(const lks_ctx *c, int mode) {
 template <typename T>
 hipError_t launch_fwd_raw(lks_ctx *c, const lks::FwdArgs<T> *dargs, long long ntiles, hipStream_t s) {
     return c->d.dim == 2 ? lks::launch_fwd2d_batch<T>(dargs, c->tile0, 1, ntiles, s)
-                         : lks::launch_fwd3d_batch<T>(dargs, c->tile0, 1, ntiles, c->d.lattice, s);
+                         : lks::launch_fwd3d_batch<T>(dargs, c->tile0, 1, ntiles, c->d.lattice, c->L.g.per[2] != 0, s);
 }
 
 // one forward step (timed as kind 0); mode is the host copy's mode
@@ -1219,7 +1219,7 @@ int round_impl(lks_batch *b, lks_ctx *const *cs, int n, int *done) {
         int kind, li;
         long long args, t0, t1, total, total1;
         int njobs;
-        bool pz = false;  // 3D adjoint: every job periodic in z
+        bool pz = false;  // 3D: every job of the launch periodic in z
     };
     std::vector<Launch> ls;
     for (int li = 0; li < 3; ++li) {
@@ -1228,6 +1228,8 @@ int round_impl(lks_batch *b, lks_ctx *const *cs, int n, int *done) {
             const long long tot = prefix(R.ptiles[li], p);
             Launch L{0, li, put(R.pre[li].data(), R.pre[li].size() * sizeof(lks::FwdArgs<T>)),
                      put(p.data(), p.size() * 8), 0, tot, 0, (int)R.pre[li].size()};
+            L.pz = true;
+            for (const auto &fj : R.pre[li]) L.pz = L.pz && fj.g.per[2] != 0;
             ls.push_back(L);
         }
     }
@@ -1237,6 +1239,8 @@ int round_impl(lks_batch *b, lks_ctx *const *cs, int n, int *done) {
             const long long tot = prefix(R.ftiles[li], p);
             Launch L{0, li, put(R.fwd[li].data(), R.fwd[li].size() * sizeof(lks::FwdArgs<T>)),
                      put(p.data(), p.size() * 8), 0, tot, 0, (int)R.fwd[li].size()};
+            L.pz = true;
+            for (const auto &fj : R.fwd[li]) L.pz = L.pz && fj.g.per[2] != 0;
             ls.push_back(L);
         }
         if (!R.adj[li].empty()) {
@@ -1277,7 +1281,8 @@ int round_impl(lks_batch *b, lks_ctx *const *cs, int n, int *done) {
         if (L.kind == 0) {
             const auto *a = reinterpret_cast<const lks::FwdArgs<T> *>(dv + L.args);
             e = L.li == 0 ? lks::launch_fwd2d_batch<T>(a, t0, L.njobs, L.total, b->stream)
-                          : lks::launch_fwd3d_batch<T>(a, t0, L.njobs, L.total, L.li == 1 ? LKS_D3Q19 : LKS_D3Q15, b->stream);
+                          : lks::launch_fwd3d_batch<T>(a, t0, L.njobs, L.total, L.li == 1 ? LKS_D3Q19 : LKS_D3Q15, L.pz,
+                                                       b->stream);
         } else if (L.kind == 1) {
             const auto *a = reinterpret_cast<const lks::AdjArgs<T> *>(dv + L.args);
             e = L.li == 0 ? lks::launch_adj2d_batch<T>(a, t0, L.njobs, L.total, b->stream)

@@ -104,14 +104,31 @@ __device__ __forceinline__ T d_lo(T f0, T f1, T f2) { return T(-1.5) * f0 + T(2)
 template <typename T>
 __device__ __forceinline__ T d_hi(T f0, T f1, T f2) { return T(1.5) * f0 - T(2) * f1 + T(0.5) * f2; }
 
+// LDS of the z-marching forward: a ring of velocity planes (halo 2), then the E_i plane (halo 1)
+// of every moving direction; the rest population E_0 is pulled only by its own node, which
+// evaluates it itself.  Five velocity planes in general (one-sided z differences at z faces),
+// three when the domain is periodic in z; with three, four blocks share a CU (FP32 D3Q19).
 template <typename T, int Q>
-__device__ __forceinline__ void fwd3d_body(const FwdArgs<T> &a, int bx, int by, int bz, long long blin) {
+struct Fwd3Lds {
+    static constexpr int TX = Tile3<T>::TX, TY = Tile3<T>::TY;
+    static constexpr int UX = TX + 4, UY = TY + 4, UP = UX * UY;
+    static constexpr int EX = TX + 2, EY = TY + 2, EP = EX * EY;
+    static constexpr size_t bytes(bool pz) { return (size_t)((pz ? 3 : 5) * 3 * UP + (Q - 1) * EP) * sizeof(T); }
+};
+
+template <bool PZ>
+__device__ __forceinline__ int uring(int z) { return PZ ? ring3(z) : ring5(z); }
+
+template <typename T, int Q, bool PZ>
+__device__ __forceinline__ void fwd3d_body(const FwdArgs<T> &a, int bx, int by, int bz, long long blin, T *lds) {
     constexpr int TX = Tile3<T>::TX, TY = Tile3<T>::TY, ZC = Tile3<T>::ZC, NT = TX * TY;
     constexpr int UX = TX + 4, UY = TY + 4, UP = UX * UY;  // velocity plane, halo 2
     constexpr int EX = TX + 2, EY = TY + 2, EP = EX * EY;  // E_i plane, halo 1
     constexpr int NU = (UP + NT - 1) / NT, NE = (EP + NT - 1) / NT;
-    __shared__ T su[5][3][UP];
-    __shared__ T sE[Q][EP];
+    constexpr int NR = PZ ? 3 : 5;  // velocity planes in the ring
+    constexpr int LA = PZ ? 2 : 3;  // the plane committed after the E pass of plane zc is zc + LA
+    T(*su)[3][UP] = reinterpret_cast<T(*)[3][UP]>(lds);
+    T(*sE)[EP] = reinterpret_cast<T(*)[EP]>(lds + NR * 3 * UP);  // row q - 1 holds E_q
     __shared__ double sh[NT / 64];
 
     const Geom &g = a.g;
@@ -207,7 +224,7 @@ __device__ __forceinline__ void fwd3d_body(const FwdArgs<T> &a, int bx, int by, 
         }
     };
     auto commit_u = [&](T(&ureg)[NU][3], int zp) {
-        const int sl = ring5(zp);
+        const int sl = uring<PZ>(zp);
 #pragma unroll
         for (int k = 0; k < NU; ++k) {
             const int i = tid + k * NT;
@@ -230,13 +247,15 @@ __device__ __forceinline__ void fwd3d_body(const FwdArgs<T> &a, int bx, int by, 
         }
     };
 
-    for (int zp = zs - 3; zp <= zs + 1; ++zp) {
+    // the first E plane (zs - 1) reads velocity planes zs - 1 - NR / 2 .. zs - 1 + NR / 2
+    for (int zp = zs - 1 - NR / 2; zp <= zs - 1 + NR / 2; ++zp) {
         fetch_u(ua, zp);
         commit_u(ua, zp);
     }
     fetch_r(zs - 1);
-    fetch_u(ua, zs + 2);  // committed by the first iteration
+    fetch_u(ua, zs - 1 + LA);  // committed by the first iteration
     __syncthreads();
+    const int own_u = (oy + 2) * UX + (ox + 2);  // this thread's output column in a velocity plane
 
     T acc[3][4];
 #pragma unroll
@@ -262,16 +281,22 @@ __device__ __forceinline__ void fwd3d_body(const FwdArgs<T> &a, int bx, int by, 
             const T kv = kst[ok ? ooff + (long long)zo * sz : 0];
             ks = ok ? kv : T(0);
         }
+        // rho - 1 of this thread's own node in plane zc, for its rest population
+        int zwc = zc;
+        const bool zinc = wrapc(zwc, nz, g.per[2]) && out_ok;
+        const T rown_v = rin[zinc ? ooff + (long long)zwc * sz : 0];
+        const T rown = zinc ? rown_v : T(0);
         T rcur[NE];
 #pragma unroll
         for (int k = 0; k < NE; ++k) rcur[k] = rreg[k];
-        fetch_u(uload, zc + 4);  // committed by the next iteration
+        fetch_u(uload, zc + 1 + LA);  // committed by the next iteration
         fetch_r(zc + 1);
         int zw = zc;
         const bool zin = wrapc(zw, nz, g.per[2]);
         if (zin) {
-            const int s0 = ring5(zc), sm1 = ring5(zc - 1), sp1 = ring5(zc + 1), sm2 = ring5(zc - 2),
-                      sp2 = ring5(zc + 2);
+            // (planes zc +- 2 only for the one-sided rows at z faces, never in a z-periodic ring)
+            const int s0 = uring<PZ>(zc), sm1 = uring<PZ>(zc - 1), sp1 = uring<PZ>(zc + 1),
+                      sm2 = uring<PZ>(zc - 2), sp2 = uring<PZ>(zc + 2);
             const bool zlo = !g.per[2] && zw == 0, zhi = !g.per[2] && zw == nz - 1;
 #pragma unroll
             for (int k = 0; k < NE; ++k) {
@@ -301,7 +326,6 @@ __device__ __forceinline__ void fwd3d_body(const FwdArgs<T> &a, int bx, int by, 
                     for (int qq = pp; qq < 3; ++qq)
                         tt[pp][qq] = T(4.5) * u[pp] * u[qq] + A * (du[pp][qq] + du[qq][pp]);
                 const int i = tid + k * NT;
-                sE[0][i] = T(wq<Q>(0)) * a0;
                 // +c and -c share the even part a0 + c.T.c; the odd part 3 c.u changes sign
 #pragma unroll
                 for (int q = 1; q < Q; ++q) {
@@ -312,19 +336,27 @@ __device__ __forceinline__ void fwd3d_body(const FwdArgs<T> &a, int bx, int by, 
                     T ev = a0 + T(cx * cx) * tt[0][0] + T(cy * cy) * tt[1][1] + T(cz * cz) * tt[2][2];
                     ev += T(2 * cx * cy) * tt[0][1] + T(2 * cx * cz) * tt[0][2] + T(2 * cy * cz) * tt[1][2];
                     const T od = T(3) * (T(cx) * u[0] + T(cy) * u[1] + T(cz) * u[2]);
-                    sE[q][i] = T(wq<Q>(q)) * (ev + od);
-                    sE[opp<Q>(q)][i] = T(wq<Q>(q)) * (ev - od);
+                    sE[q - 1][i] = T(wq<Q>(q)) * (ev + od);
+                    sE[opp<Q>(q) - 1][i] = T(wq<Q>(q)) * (ev - od);
                 }
             }
         }
+        // the rest population of the own node, from its own rho and u (the commit below
+        // replaces plane zc - NR / 2, not plane zc)
+        T e0 = T(0);
+        if (zin) {
+            const T u0 = su[uring<PZ>(zc)][0][own_u], u1 = su[uring<PZ>(zc)][1][own_u];
+            const T u2 = su[uring<PZ>(zc)][2][own_u];
+            e0 = T(wq<Q>(0)) * (rown - T(1.5) * (u0 * u0 + u1 * u1 + u2 * u2));
+        }
         __syncthreads();
-        commit_u(ucommit, zc + 3);
+        commit_u(ucommit, zc + LA);
         // pull: output (x, y, zo) takes E_i from (x - cx, y - cy) in plane zo - cz
         if (zin) {
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 const int cx = cq<Q>(q, 0), cy = cq<Q>(q, 1), cz = cq<Q>(q, 2);
-                const T e = sE[q][(oy + 1 - cy) * EX + (ox + 1 - cx)];
+                const T e = q == 0 ? e0 : sE[q - 1][(oy + 1 - cy) * EX + (ox + 1 - cx)];
                 const int t = cz + 1;  // cz = -1 -> plane zc - 1, 0 -> zc, +1 -> zc + 1
                 acc[t][0] += e;
                 if (cx) acc[t][1] += T(cx) * e;
@@ -404,10 +436,13 @@ __device__ __forceinline__ long long stencil_tiles3(const Geom &g) {
            ((g.n[1] + Tile3<T>::TY - 1) / Tile3<T>::TY) * ((g.n[2] + Tile3<T>::ZC - 1) / Tile3<T>::ZC);
 }
 
-template <typename T, int Q>
+// PZ: every job of the launch is periodic in z (the three-plane velocity ring; dynamic LDS sized
+// to it).  One kernel per layout, so each gets its own register allocation.
+template <typename T, int Q, bool PZ>
 __global__ __launch_bounds__(Tile3<T>::TX * Tile3<T>::TY) void k_fwd3d_batch(const FwdArgs<T> *__restrict__ args,
                                                                             const long long *__restrict__ tile0,
                                                                             int njobs) {
+    extern __shared__ __align__(16) unsigned char fwd3_lds[];
     const long long b = blockIdx.x;
     const int j = __builtin_amdgcn_readfirstlane(job_of3(tile0, njobs, b));
     const FwdArgs<T> &a = args[j];
@@ -419,7 +454,7 @@ __global__ __launch_bounds__(Tile3<T>::TX * Tile3<T>::TY) void k_fwd3d_batch(con
     }
     int bx, by, bz;
     tile_coords3<T>(a.g, t, bx, by, bz);
-    fwd3d_body<T, Q>(a, bx, by, bz, t);
+    fwd3d_body<T, Q, PZ>(a, bx, by, bz, t, reinterpret_cast<T *>(fwd3_lds));
 }
 
 // ================================== adjoint, pointwise part ===================================
@@ -732,20 +767,19 @@ __device__ __forceinline__ void adj3d_main_body(const AdjArgs<T> &a, int bx, int
     }
 }
 
-// pz: every job of the launch is periodic in z (the smaller LDS layout; dynamic LDS sized to it)
-template <typename T, int Q>
+// PZ: every job of the launch is periodic in z (the smaller LDS layout; dynamic LDS sized to it).
+// One kernel per layout, so each gets its own register allocation.
+template <typename T, int Q, bool PZ>
 __global__ __launch_bounds__(Tile3<T>::TX * Tile3<T>::TY) void k_adj3d_main_batch(const AdjArgs<T> *__restrict__ args,
                                                                                  const long long *__restrict__ tile0,
-                                                                                 int njobs, int pz) {
+                                                                                 int njobs) {
     extern __shared__ __align__(16) unsigned char adj3_lds[];
     const long long b = blockIdx.x;
     const int j = __builtin_amdgcn_readfirstlane(job_of3(tile0, njobs, b));
     const AdjArgs<T> &a = args[j];
     int bx, by, bz;
     tile_coords3<T>(a.g, njobs == 1 ? b : b - tile0[j], bx, by, bz);
-    T *lds = reinterpret_cast<T *>(adj3_lds);
-    if (pz) adj3d_main_body<T, Q, true>(a, bx, by, bz, lds);
-    else adj3d_main_body<T, Q, false>(a, bx, by, bz, lds);
+    adj3d_main_body<T, Q, PZ>(a, bx, by, bz, reinterpret_cast<T *>(adj3_lds));
 }
 
 long long fwd_blocks3d(const Geom &g, int lattice, int esz) {
@@ -765,11 +799,15 @@ long long xfer_blocks3d(long long cells, int esz) {
 
 template <typename T>
 hipError_t launch_fwd3d_batch(const FwdArgs<T> *args, const long long *tile0, int njobs,
-                              long long ntiles, int lattice, hipStream_t s) {
+                              long long ntiles, int lattice, bool pz, hipStream_t s) {
     if (njobs == 0) return hipSuccess;
     const dim3 blk(Tile3<T>::TX * Tile3<T>::TY);
-    if (lattice == 2) hipLaunchKernelGGL((k_fwd3d_batch<T, 19>), dim3((unsigned)ntiles), blk, 0, s, args, tile0, njobs);
-    else hipLaunchKernelGGL((k_fwd3d_batch<T, 15>), dim3((unsigned)ntiles), blk, 0, s, args, tile0, njobs);
+    const dim3 grid((unsigned)ntiles);
+    const unsigned lds19 = (unsigned)Fwd3Lds<T, 19>::bytes(pz), lds15 = (unsigned)Fwd3Lds<T, 15>::bytes(pz);
+    if (lattice == 2 && pz) hipLaunchKernelGGL((k_fwd3d_batch<T, 19, true>), grid, blk, lds19, s, args, tile0, njobs);
+    else if (lattice == 2) hipLaunchKernelGGL((k_fwd3d_batch<T, 19, false>), grid, blk, lds19, s, args, tile0, njobs);
+    else if (pz) hipLaunchKernelGGL((k_fwd3d_batch<T, 15, true>), grid, blk, lds15, s, args, tile0, njobs);
+    else hipLaunchKernelGGL((k_fwd3d_batch<T, 15, false>), grid, blk, lds15, s, args, tile0, njobs);
     return hipGetLastError();
 }
 
@@ -781,16 +819,17 @@ hipError_t launch_adj3d_batch(const AdjArgs<T> *args, const long long *blk0, lon
     hipLaunchKernelGGL(k_adj3d_prep_batch<T>, dim3((unsigned)nblk), dim3(kBlock), 0, s, args, blk0, njobs);
     const dim3 blk(Tile3<T>::TX * Tile3<T>::TY);
     const unsigned lds = (unsigned)Adj3Lds<T>::bytes(pz);
-    if (lattice == 2)
-        hipLaunchKernelGGL((k_adj3d_main_batch<T, 19>), dim3((unsigned)ntiles), blk, lds, s, args, tile0, njobs, (int)pz);
-    else
-        hipLaunchKernelGGL((k_adj3d_main_batch<T, 15>), dim3((unsigned)ntiles), blk, lds, s, args, tile0, njobs, (int)pz);
+    const dim3 grid((unsigned)ntiles);
+    if (lattice == 2 && pz) hipLaunchKernelGGL((k_adj3d_main_batch<T, 19, true>), grid, blk, lds, s, args, tile0, njobs);
+    else if (lattice == 2) hipLaunchKernelGGL((k_adj3d_main_batch<T, 19, false>), grid, blk, lds, s, args, tile0, njobs);
+    else if (pz) hipLaunchKernelGGL((k_adj3d_main_batch<T, 15, true>), grid, blk, lds, s, args, tile0, njobs);
+    else hipLaunchKernelGGL((k_adj3d_main_batch<T, 15, false>), grid, blk, lds, s, args, tile0, njobs);
     return hipGetLastError();
 }
 
 #define LKS_INST3(T)                                                                                  \
     template hipError_t launch_fwd3d_batch<T>(const FwdArgs<T> *, const long long *, int, long long,  \
-                                              int, hipStream_t);                                      \
+                                              int, bool, hipStream_t);                                \
     template hipError_t launch_adj3d_batch<T>(const AdjArgs<T> *, const long long *, long long,       \
                                               const long long *, long long, int, int, bool, hipStream_t);
 LKS_INST3(float)
