@@ -45,6 +45,10 @@ CASES = {
     "d3q15_cos4_paper_drag": dict(lattice="D3Q15", weight="COS4", interp="PAPER", kmax=2.0,
                                   obj="DRAG", n=(36, 34, 40), nd=(7, 7, 7)),
     "d3q19_fully_periodic_j2": dict(obj="J2", bcs=I.periodic_bcs()),
+    # walls on the z faces: the kernels' general z layout (five-plane rings, one-sided z rows)
+    "d3q19_zwalls_torque": dict(
+        bcs=[_bc("VELOCITY", 1.0, (0.03, 0, 0)), _bc("ZERO_GRADIENT"), _bc("PERIODIC"), _bc("PERIODIC"),
+             _bc("NOSLIP"), _bc("NOSLIP", 1.0, (0.01, 0, 0))]),
 }
 
 
