@@ -44,6 +44,7 @@ class Result:
     finished: float
     status: str = "ok"
     cells_steps: float = 0.0
+    alg_bytes: float = 0.0  # algorithmic HBM bytes of the evaluation (see alg_bytes)
 
     @property
     def latency(self) -> float:
@@ -129,7 +130,7 @@ class Server:
                     cfg = a.req.cfg
                     results.append(Result(a.req.rid, J, a.out.cpu().numpy(), a.req.arrival,
                                           a.admitted, fin, status,
-                                          float(np.prod(cfg["n"])) * cfg["nsteps"]))
+                                          float(np.prod(cfg["n"])) * cfg["nsteps"], alg_bytes(cfg)))
                     a.solver.close()
                     used -= a.nbytes
                     active.remove(a)
@@ -165,8 +166,24 @@ def serve_plain(requests: List[Request]) -> List[Result]:
             torch.cuda.synchronize()
         fin = time.perf_counter() - t0
         results.append(Result(rq.rid, J, out.cpu().numpy(), rq.arrival, start, fin, status,
-                              float(np.prod(rq.cfg["n"])) * rq.cfg["nsteps"]))
+                              float(np.prod(rq.cfg["n"])) * rq.cfg["nsteps"], alg_bytes(rq.cfg)))
     return sorted(results, key=lambda r: r.rid)
+
+
+HBM_PEAK_GBS = 8000.0
+
+
+def alg_bytes(cfg: dict) -> float:
+    """Algorithmic HBM bytes of one sensitivity evaluation: every forward step (sweep and segment
+    recompute) reads and writes rho and u, every adjoint step reads lambda and u^{n-1} and writes
+    lambda.  The footprint box and the design grid are not counted (under 2 B per update)."""
+    e = 8 if cfg["precision"] == "F64" else 4
+    D, N = cfg["dim"], cfg["nsteps"]
+    cells = float(np.prod(cfg["n"]))
+    K = cfg.get("checkpoint_every") or 0
+    recomputed = 0 if K <= 0 else N - (N - ((N - 1) // K) * K)  # every segment but the last
+    fwd, adj = 2 * (1 + D) * e, (2 * (1 + D) + D) * e
+    return cells * ((N + recomputed) * fwd + N * adj)
 
 
 def summarize(results: List[Result]) -> dict:
@@ -179,4 +196,6 @@ def summarize(results: List[Result]) -> dict:
             "evals_per_s": len(ok) / span if span > 0 else float("nan"),
             "p50_latency_s": float(np.percentile(lat, 50)),
             "p99_latency_s": float(np.percentile(lat, 99)),
-            "mlups": sum(r.cells_steps for r in ok) / span / 1e6 if span > 0 else float("nan")}
+            "mlups": sum(r.cells_steps for r in ok) / span / 1e6 if span > 0 else float("nan"),
+            "achieved_gbs": sum(r.alg_bytes for r in ok) / span / 1e9 if span > 0 else float("nan"),
+            "hbm_frac": sum(r.alg_bytes for r in ok) / span / 1e9 / HBM_PEAK_GBS if span > 0 else float("nan")}
