@@ -316,10 +316,6 @@ __host__ __device__ inline int fwd2d_grid_x(const Geom &g) {
 }
 __host__ __device__ inline int fwd2d_grid_y(const Geom &g) { return (g.n[1] + RY - 1) / RY; }
 
-// Row chunk of the r-th dispatched chunk row out of gy: alternately from both ends, so the waves
-// that touch the y faces (slower code) start early instead of forming the tail of the launch.
-__device__ __forceinline__ int chunk_row(int r, int gy) { return (r & 1) ? gy - 1 - (r >> 1) : (r >> 1); }
-
 // first tile of the job that owns flat tile b (tile0 ascending, tile0[0] = 0)
 __device__ __forceinline__ int job_of(const long long *tile0, int njobs, long long b) {
     int lo = 0, hi = njobs - 1;
@@ -381,17 +377,7 @@ __device__ __forceinline__ T deriv_T(const T f[5], int c, int n, int per) {
 // Every lane that a needed P* sits on has both neighbours inside the wave, so the boundary
 // seeds of column-adjacent faces come from lane shifts as well.
 constexpr int SWA = 58;  // output columns per adjoint wave strip
-#ifndef LKS_ADJ2D_RY
-#define LKS_ADJ2D_RY 2
-#endif
-constexpr int RYA = LKS_ADJ2D_RY;  // output rows per wave
-constexpr int RGA = 2;   // rows per pass in waves that touch a face or wrap
-
-__host__ __device__ inline int adj2d_grid_x(const Geom &g) {
-    const int nstrips = (g.n[0] + SWA - 1) / SWA;
-    return (nstrips + WPB - 1) / WPB;
-}
-__host__ __device__ inline int adj2d_grid_y(const Geom &g) { return (g.n[1] + RYA - 1) / RYA; }
+constexpr int RGA = 2;   // output rows of a general unit (faces, wraps)
 
 template <typename T, bool IN, int NR>
 __device__ __forceinline__ void adj2d_rows(const AdjArgs<T> &a, int strip, int y0) {
@@ -653,21 +639,227 @@ __device__ __forceinline__ void adj2d_rows(const AdjArgs<T> &a, int strip, int y
     }
 }
 
-template <typename T>
-__device__ __forceinline__ void adj2d_body(const AdjArgs<T> &a, int bx, int by) {
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar branches
+// Interior adjoint rows as one march along y.  The wave's output rows y0 .. y0 + RM - 1 need
+// lambda rows y0 - 2 .. y0 + RM + 1; every one of them, and every lane's column, is at least two
+// nodes from a face and needs no wrap, so there are no boundary seeds and every derivative is
+// central.  lambda row r = y0 - 2 + j is requested AH rows before it is used; once it arrives it
+// becomes (P*, V*) and its x-stencils, which complete moment row r - 1 (three stencil rows), which
+// completes output row r - 2 (three moment rows).  Each row is loaded and transposed once.
+#ifndef LKS_ADJ2D_AHEAD
+#define LKS_ADJ2D_AHEAD 3
+#endif
+template <typename T, int RM, bool WB>
+__device__ __forceinline__ void adj2d_march(const AdjArgs<T> &a, int strip, int y0) {
+    constexpr int NJ = RM + 4;
+    constexpr int AH = LKS_ADJ2D_AHEAD;
+    const int lane = threadIdx.x & 63;
     const Geom &g = a.g;
-    const int nx = g.n[0], ny = g.n[1];
-    const int strip = bx * WPB + w;
-    if (strip >= (nx + SWA - 1) / SWA) return;
-    const int y0 = by * RYA, cmin = strip * SWA - 3;
-    if (cmin >= 1 && cmin + 63 <= nx - 2 && y0 >= 4 && y0 + RYA <= ny - 4) {
-        adj2d_rows<T, true, RYA>(a, strip, y0);
-    } else {
-#pragma unroll 1
-        for (int s = 0; s < RYA / RGA; ++s)
-            if (y0 + s * RGA < ny) adj2d_rows<T, false, RGA>(a, strip, y0 + s * RGA);
+    const int sy = (int)g.sy;  // grids hold fewer than 2^31 nodes
+    const int c = strip * SWA - 3 + lane;
+    const bool out_lane = lane >= 3 && lane <= 60;
+    const bool obj_on = a.obj.active && a.obj.kind != OBJ_NONE;
+    const bool kobj = obj_on && obj_uses_kappa(a.obj.kind);
+    const bool seeds = obj_on && (WB || !kobj);  // kappa objectives vanish off the footprint
+    const double sc = a.obj.scale;
+    const LKS_GLOBAL T *__restrict__ Pin = gld(a.Pin);
+    const LKS_GLOBAL T *__restrict__ Vin0 = gld(a.Vin[0]);
+    const LKS_GLOBAL T *__restrict__ Vin1 = gld(a.Vin[1]);
+    const LKS_GLOBAL T *__restrict__ up0 = gld(a.uprev[0]);
+    const LKS_GLOBAL T *__restrict__ up1 = gld(a.uprev[1]);
+    const LKS_GLOBAL T *__restrict__ kst = gld(a.kstatic);
+    const LKS_GLOBAL uint8_t *__restrict__ omask = gld(a.obj.mask);
+    const bool want_mask = obj_on && omask != nullptr;
+    const bool brink = WB || kst != nullptr;
+
+    // loads of lambda row j (and what the same slot carries: kappa, u_S and u^n of that row on the
+    // footprint, u^{n-1} of output row j - 2), AH slots in flight
+    T qp[AH], qx[AH], qy[AH], qk[AH], qs0[AH], qs1[AH], qc0[AH], qc1[AH], qu0[AH], qu1[AH], qks[AH];
+    uint8_t qm[AH];
+    auto issue = [&](int j) {
+        const int s = j % AH;
+        const int r = y0 - 2 + j;
+        const int idx = c + r * sy;
+        qp[s] = Pin[idx];
+        qx[s] = Vin0[idx];
+        qy[s] = Vin1[idx];
+        if (WB) {
+            const int bi = box_index2_clamped(a.box, a.m, c, r);
+            qk[s] = gld(a.kbox)[bi];
+            qs0[s] = gld(a.usbox[0])[bi];
+            qs1[s] = gld(a.usbox[1])[bi];
+            if (j >= 2 && j < RM + 2) {  // u^n of an output row, at a box node (inside the grid)
+                const int cx = min(max(c, a.m.lo[0]), a.m.hi[0]), cy = min(max(r, a.m.lo[1]), a.m.hi[1]);
+                const int ib = cx + cy * sy;
+                qc0[s] = gld(a.ucur[0])[ib];
+                qc1[s] = gld(a.ucur[1])[ib];
+            }
+        }
+        if (j >= 4) {  // u^{n-1} of output row r - 2
+            const int io = idx - 2 * sy;
+            qu0[s] = up0[io];
+            qu1[s] = up1[io];
+        }
+        if (kst) qks[s] = kst[idx];
+        if (want_mask) qm[s] = omask[idx];
+    };
+
+    const T s6 = T(1) / T(6), t3 = T(2) / T(3);
+    const T A2 = T(2) * a.A;
+    T xs[3][6];   // x-stencil rows (a0, a1, a2, b0, b1, b2), ring by row
+    T mo[3][6];   // moment rows (rho~, u~x, u~y, s~xx, s~xy, s~yy), ring by row
+#pragma unroll
+    for (int j = 0; j < AH && j < NJ; ++j) issue(j);
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const int s = j % AH;
+        const int r = y0 - 2 + j;
+        T P = qp[s], Vx = qx[s], Vy = qy[s];
+        const bool inb = WB && in_box(a.m, 2, c, r, 0);
+        const T kap = inb ? qk[s] : T(0), usx = inb ? qs0[s] : T(0), usy = inb ? qs1[s] : T(0);
+        const T ucx = inb ? qc0[s] : T(0), ucy = inb ? qc1[s] : T(0);
+        const T upx = qu0[s], upy = qu1[s];
+        const T ks = kst ? qks[s] : T(0);
+        const bool mk = want_mask ? qm[s] != 0 : true;
+        if (j + AH < NJ) issue(j + AH);
+
+        // lambda + dj/dX, then the force transpose
+        if (seeds && mk && !(kobj && kap == T(0))) {
+            const double us[3] = {(double)usx, (double)usy, 0.0};
+            double dP, dV[3];
+            obj_dstate(a.obj, c, r, 0, (double)kap, us, dP, dV);
+            P += (T)(sc * dP);
+            Vx += (T)(sc * dV[0]);
+            Vy += (T)(sc * dV[1]);
+        }
+        if (brink) {
+            const T inv = rcp_t(T(1) + kap + ks);
+            Vx *= inv;
+            Vy *= inv;
+        }
+        // kappa_bar on the wave's own footprint nodes of its output rows
+        if (WB && j >= 2 && j < RM + 2 && out_lane && inb) {
+            double kb = -((double)Vx * ((double)ucx - (double)usx) + (double)Vy * ((double)ucy - (double)usy));
+            if (kobj && mk) {
+                const double uu[3] = {(double)ucx, (double)ucy, 0.0};
+                const double uss[3] = {(double)usx, (double)usy, 0.0};
+                kb += sc * obj_dkappa(a.obj, c, r, 0, uu, uss);
+            }
+            gst(a.kbar)[box_index(a.box, a.m, 2, c, r, 0)] = (T)kb;
+        }
+
+        // x-stencils of row r: a0 = M0 P + M1 Vx, a1 = M1 P + M2 Vx, a2 = M2 P + M1 Vx, b_k = M_k Vy
+        {
+            T *x = xs[j % 3];
+            const T pl = from_left(P), pr = from_right(P);
+            const T vxl = from_left(Vx), vxr = from_right(Vx);
+            const T vyl = from_left(Vy), vyr = from_right(Vy);
+            const T m0p = t3 * P + s6 * (pr + pl), m1p = s6 * (pr - pl), m2p = s6 * (pr + pl);
+            const T m1x = s6 * (vxr - vxl), m2x = s6 * (vxr + vxl);
+            x[0] = m0p + m1x;
+            x[1] = m1p + m2x;
+            x[2] = m2p + m1x;
+            x[3] = t3 * Vy + s6 * (vyr + vyl);
+            x[4] = s6 * (vyr - vyl);
+            x[5] = s6 * (vyr + vyl);
+        }
+        // moment row r - 1 from stencil rows r - 2, r - 1, r
+        if (j >= 2) {
+            const T *xm = xs[(j - 2) % 3], *x0 = xs[(j - 1) % 3], *xp = xs[j % 3];
+            T *m = mo[(j - 1) % 3];
+            const T sa0 = xp[0] + xm[0], da0 = xp[0] - xm[0];
+            const T sa1 = xp[1] + xm[1], da1 = xp[1] - xm[1];
+            const T sa2 = xp[2] + xm[2];
+            const T sb0 = xp[3] + xm[3], db0 = xp[3] - xm[3];
+            const T sb1 = xp[4] + xm[4], db1 = xp[4] - xm[4];
+            const T db2 = xp[5] - xm[5];
+            m[5] = s6 * (sa0 + db0);
+            m[0] = t3 * x0[0] + m[5];
+            m[1] = t3 * x0[1] + s6 * (sa1 + db1);
+            m[3] = t3 * x0[2] + s6 * (sa2 + db2);
+            m[2] = s6 * (da0 + sb0);
+            m[4] = s6 * (da1 + sb1);
+        }
+        // Lambda^{n-1} on output row r - 2 from moment rows r - 3, r - 2, r - 1
+        if (j >= 4) {
+            const T *mm = mo[(j - 3) % 3], *m0 = mo[(j - 2) % 3], *mp = mo[(j - 1) % 3];
+            const T xxl = from_left(m0[3]), xxr = from_right(m0[3]);
+            const T xyl = from_left(m0[4]), xyr = from_right(m0[4]);
+            const T dxx = T(0.5) * (xxl - xxr);
+            const T dxy = T(0.5) * (xyl - xyr);
+            const T dyxy = T(0.5) * (mm[4] - mp[4]);
+            const T dyyy = T(0.5) * (mm[5] - mp[5]);
+            const T rt = m0[0];
+            T vx = T(3) * m0[1] + T(9) * (m0[3] * upx + m0[4] * upy) - T(3) * rt * upx;
+            T vy = T(3) * m0[2] + T(9) * (m0[4] * upx + m0[5] * upy) - T(3) * rt * upy;
+            vx += A2 * dxx;
+            vx += A2 * dyxy;
+            vy += A2 * dxy;
+            vy += A2 * dyyy;
+            if (out_lane) {
+                const int io = c + (r - 2) * sy;
+                gst(a.Pout)[io] = rt;
+                gst(a.Vout[0])[io] = vx;
+                gst(a.Vout[1])[io] = vy;
+            }
+        }
     }
+}
+
+// Work units of one 2D adjoint step, one per wave.  Inner strips (every lane's column at least one
+// node off the x faces, no wrap) march RMA rows at a time over rows [4, yhi); every other
+// (strip, row pair) — strips that touch an x face or wrap, and the four rows next to each y face or
+// wrap — is a general unit of RGA rows with the full boundary transpose.  March units come first,
+// then general units of the outer strips, then the y-edge units of the inner strips.
+#ifndef LKS_ADJ2D_RM
+#define LKS_ADJ2D_RM 8
+#endif
+constexpr int RMA = LKS_ADJ2D_RM;
+struct Adj2dUnits {
+    int nstrips, ninner, nmc, yhi, ngs, ngr, neg;
+    long long nmarch, nouter, total;
+};
+__host__ __device__ inline Adj2dUnits adj2d_units(const Geom &g) {
+    Adj2dUnits u;
+    const int nx = g.n[0], ny = g.n[1];
+    u.nstrips = (nx + SWA - 1) / SWA;
+    u.nmc = ny >= 8 ? (ny - 8) / RMA : 0;
+    u.ninner = (u.nmc > 0 && nx >= 2 * SWA + 4) ? (nx - 62) / SWA : 0;
+    if (u.ninner == 0) u.nmc = 0;
+    u.yhi = 4 + RMA * u.nmc;
+    u.ngs = u.nstrips - u.ninner;
+    u.ngr = (ny + RGA - 1) / RGA;
+    u.neg = u.ninner > 0 ? 2 + (ny - u.yhi + RGA - 1) / RGA : 0;
+    u.nmarch = (long long)u.ninner * u.nmc;
+    u.nouter = (long long)u.ngs * u.ngr;
+    u.total = u.nmarch + u.nouter + (long long)u.ninner * u.neg;
+    return u;
+}
+
+template <typename T>
+__device__ __forceinline__ void adj2d_unit(const AdjArgs<T> &a, const Adj2dUnits &u, long long k) {
+    if (k < u.nmarch) {
+        const int kk = (int)k;
+        const int strip = 1 + kk % u.ninner, y0 = 4 + RMA * (kk / u.ninner);
+        const int cmin = strip * SWA - 3;
+        const bool wbox = a.m.hi[0] >= cmin && a.m.lo[0] <= cmin + 63 && a.m.hi[1] >= y0 - 2 &&
+                          a.m.lo[1] <= y0 + RMA + 1;
+        if (wbox) adj2d_march<T, RMA, true>(a, strip, y0);
+        else adj2d_march<T, RMA, false>(a, strip, y0);
+        return;
+    }
+    int strip, y0;
+    if (k < u.nmarch + u.nouter) {
+        const int v = (int)(k - u.nmarch);
+        const int q = v % u.ngs;
+        strip = q == 0 ? 0 : u.ninner + q;
+        y0 = RGA * (v / u.ngs);
+    } else {
+        const int v = (int)(k - u.nmarch - u.nouter);
+        const int q = v / u.ninner;
+        strip = 1 + v % u.ninner;
+        y0 = q < 2 ? RGA * q : u.yhi + RGA * (q - 2);
+    }
+    adj2d_rows<T, false, RGA>(a, strip, y0);
 }
 
 #ifndef LKS_ADJ2D_WAVES
@@ -682,14 +874,14 @@ __global__ __launch_bounds__(kBlock, LKS_ADJ2D_WAVES) void k_adj2d_batch(const A
     const int j = __builtin_amdgcn_readfirstlane(job_of(tile0, njobs, b));
     const AdjArgs<T> &a = args[j];
     const long long t = njobs == 1 ? b : b - tile0[j];  // one job: tile0 = {0}
-    const int nbx = adj2d_grid_x(a.g);
-    const long long na = (long long)nbx * adj2d_grid_y(a.g);
+    const Adj2dUnits u = adj2d_units(a.g);
+    const long long na = (u.total + WPB - 1) / WPB;
     if (t >= na) {  // extra blocks: sensitivity gather of the previous adjoint step
         sens_body<T>(*a.sens, t - na);
         return;
     }
-    // (XCD banding as in the forward measured slower here: 26.9 vs 25.8 us at 1024^2)
-    adj2d_body<T>(a, (int)((unsigned)t % (unsigned)nbx), chunk_row((int)((unsigned)t / (unsigned)nbx), adj2d_grid_y(a.g)));
+    const long long k = t * WPB + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (k < u.total) adj2d_unit<T>(a, u, k);
 }
 
 long long fwd_blocks(const Geom &g, int lattice, int esz) {
@@ -704,7 +896,7 @@ long long xfer_blocks(int dim, long long cells, int esz) {
 }
 
 long long tiles2d_fwd(const Geom &g) { return (long long)fwd2d_grid_x(g) * fwd2d_grid_y(g); }
-long long tiles2d(const Geom &g) { return (long long)adj2d_grid_x(g) * adj2d_grid_y(g); }
+long long tiles2d(const Geom &g) { return (adj2d_units(g).total + WPB - 1) / WPB; }
 
 template <typename T>
 hipError_t launch_fwd2d_batch(const FwdArgs<T> *args, const long long *tile0, int njobs,

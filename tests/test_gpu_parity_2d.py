@@ -23,7 +23,8 @@ def _bc(kind, rho=1.0, u=(0.0, 0.0, 0.0)):
 
 
 def small(n=(70, 37), nd=(14, 12), N=60, K=0, prec="F64", obj="DRAG", weight="LIN",
-          interp="FLUID_ONE", bcs=None, motion="rotate", mask=None, norm=1, kmax=0.5, nu=0.04):
+          interp="FLUID_ONE", bcs=None, motion="rotate", mask=None, norm=1, kmax=0.5, nu=0.04,
+          kappa_static=None, body_force=(0.0, 0.0, 0.0)):
     centre = ((n[0] - 1) / 2.0 + 0.3, (n[1] - 1) / 2.0 - 0.2, 0.0)
     if motion == "rotate":
         mot = I.motion_rotation(N, centre, 2 * math.pi / 90)
@@ -35,7 +36,8 @@ def small(n=(70, 37), nd=(14, 12), N=60, K=0, prec="F64", obj="DRAG", weight="LI
                                          direction=(0.8, 0.6, 0.0) if obj != "TORQUE" else (0, 0, 1),
                                          mask=mask),
                          u0=(0.03, 0, 0), weight=weight, interp=interp, kappa_max=kmax,
-                         precision=prec, checkpoint_every=K)
+                         precision=prec, checkpoint_every=K, kappa_static=kappa_static,
+                         body_force=body_force)
 
 
 def test_c1_fp64_full():
@@ -82,6 +84,41 @@ def test_variants_fp64(name):
     cfg = small(K=13, **CASES[name])
     announce(f"variant {name}")
     g = I.gamma_field(cfg["nd"], 2, 3)
+    compare(cfg, g, **F64)
+
+
+def _static_solid(n, seed=8):
+    """A few static solid discs (kappa_s = 0.3) away from the moving body."""
+    rng = np.random.default_rng(seed)
+    ks = np.zeros(n[::-1])
+    yy, xx = np.mgrid[0:n[1], 0:n[0]]
+    for _ in range(4):
+        cx, cy, r = rng.uniform(0.1, 0.3) * n[0], rng.uniform(0.2, 0.8) * n[1], rng.uniform(2, 5)
+        ks[np.hypot(xx - cx, yy - cy) <= r] = 0.3
+    return ks.reshape(-1)
+
+
+# A grid wide and tall enough for interior waves that march several rows (inner strips of 58
+# columns at least one node off the x faces, rows 4 .. ny - 5): the rotating body's footprint
+# meets some of them and not others, so both kinds of march run next to the face units.
+WIDE = (181, 45)
+WIDE_CASES = dict(CASES)
+WIDE_CASES["j1_mask"] = dict(obj="J1", norm=3)
+WIDE_CASES["static_solid_force"] = dict(obj="POWER", kappa_static=_static_solid(WIDE),
+                                        body_force=(2e-6, -1e-6, 0.0))
+
+
+@pytest.mark.parametrize("name", sorted(WIDE_CASES))
+def test_variants_wide_fp64(name):
+    kw = dict(WIDE_CASES[name])
+    if name == "j1_mask":  # a band of the interior and a piece of the outlet face
+        mask = np.zeros(WIDE[::-1], dtype=np.uint8)
+        mask[10:30, 120:170] = 1
+        mask[:, -1] = 1
+        kw["mask"] = mask.reshape(-1)
+    cfg = small(n=WIDE, nd=(20, 16), N=40, K=11, **kw)
+    announce(f"wide variant {name}")
+    g = I.gamma_field(cfg["nd"], 2, 7)
     compare(cfg, g, **F64)
 
 
