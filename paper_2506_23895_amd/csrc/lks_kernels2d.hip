@@ -52,8 +52,9 @@ __device__ __forceinline__ double from_right(double v) {
 
 // Forward step as wave strips marching along y.  Lane l of wave w holds column
 // c = 60 * strip - 2 + l; lanes 2..61 produce outputs, lanes 0, 1, 62, 63 are the column halo.
-// A wave owns RY output rows: it issues the loads of every velocity row it needs (RY + 5) and
-// every density row (RY + 2) into registers up front, then walks the rows as they arrive.  Per
+// A wave owns NR output rows (RY in the interior, RF next to faces): it issues the loads of every
+// velocity row it needs (NR + 5) and every density row (NR + 2) into registers up front, then
+// walks the rows as they arrive.  Per
 // row r the lane evaluates the strain and the nine E_i of its own node once, adds the ones pulled
 // by its own column (c_x = 0) into three in-flight output rows, and sums per target row the ones
 // pulled by column c+1 (c_x = +1) and by column c-1 (c_x = -1); those sums reach the neighbouring
@@ -92,7 +93,7 @@ __device__ __forceinline__ double rcp_t(double v) { return 1.0 / v; }
 // IN: the wave touches no face, needs no periodic wrap and every E row it evaluates has central
 // differences on both axes (decided per wave), so the bounds, wrap, one-sided and boundary-push
 // code is compiled out.
-template <typename T, bool IN>
+template <typename T, bool IN, int NR>
 __device__ __forceinline__ void fwd2d_rows(const FwdArgs<T> &a, int strip, int y0, long long pslot,
                                            bool obj_on) {
     const int lane = threadIdx.x & 63;
@@ -114,14 +115,14 @@ __device__ __forceinline__ void fwd2d_rows(const FwdArgs<T> &a, int strip, int y
     const LKS_GLOBAL uint8_t *__restrict__ omask = gld(a.obj.mask);
     // does this wave's rectangle meet the footprint box (wave-uniform)?
     const bool wbox = a.m.hi[0] >= strip * SW && a.m.lo[0] < strip * SW + SW && a.m.hi[1] >= y0 &&
-                      a.m.lo[1] < y0 + RY;
+                      a.m.lo[1] < y0 + NR;
     const bool brink = wbox || a.kstatic != nullptr;  // kappa + kappa_s can be non-zero here
 
     // every row this wave needs, requested before any arithmetic
-    T ux[RY + 5], uy[RY + 5], rv[RY + 2];
-    T kb[RY], sbx[RY], sby[RY];  // kappa, u_S of the output rows (footprint waves only)
+    T ux[NR + 5], uy[NR + 5], rv[NR + 2];
+    T kb[NR], sbx[NR], sby[NR];  // kappa, u_S of the output rows (footprint waves only)
 #pragma unroll
-    for (int k = 0; k < RY + 5; ++k) {
+    for (int k = 0; k < NR + 5; ++k) {
         int yw = y0 - 3 + k;
         ux[k] = uy[k] = T(0);
         if (IN) {
@@ -138,7 +139,7 @@ __device__ __forceinline__ void fwd2d_rows(const FwdArgs<T> &a, int strip, int y
         }
     }
 #pragma unroll
-    for (int k = 0; k < RY + 2; ++k) {
+    for (int k = 0; k < NR + 2; ++k) {
         int yw = y0 - 1 + k;
         rv[k] = T(0);
         if (IN) {
@@ -154,18 +155,18 @@ __device__ __forceinline__ void fwd2d_rows(const FwdArgs<T> &a, int strip, int y
     // branch), all loads are issued before the first select, and the field rows above are already
     // in flight while they wait
 #pragma unroll
-    for (int k = 0; k < RY; ++k) kb[k] = sbx[k] = sby[k] = T(0);
+    for (int k = 0; k < NR; ++k) kb[k] = sbx[k] = sby[k] = T(0);
     if (wbox) {  // wave-uniform
-        T k0[RY], s0[RY], s1[RY];
+        T k0[NR], s0[NR], s1[NR];
 #pragma unroll
-        for (int k = 0; k < RY; ++k) {
+        for (int k = 0; k < NR; ++k) {
             const int bi = box_index2_clamped(a.box, a.m, c, y0 + k);
             k0[k] = gld(a.kin)[bi];
             s0[k] = gld(a.usin[0])[bi];
             s1[k] = gld(a.usin[1])[bi];
         }
 #pragma unroll
-        for (int k = 0; k < RY; ++k) {
+        for (int k = 0; k < NR; ++k) {
             const bool inb = in_box(a.m, 2, c, y0 + k, 0);
             kb[k] = inb ? k0[k] : T(0);
             sbx[k] = inb ? s0[k] : T(0);
@@ -181,7 +182,7 @@ __device__ __forceinline__ void fwd2d_rows(const FwdArgs<T> &a, int strip, int y
     const T wa = T(d2q9::WA), wd = T(d2q9::WD), w0 = T(d2q9::W0);
 
 #pragma unroll
-    for (int e = 0; e < RY + 2; ++e) {
+    for (int e = 0; e < NR + 2; ++e) {
         const int r = y0 - 1 + e;  // row of the E_i evaluated now; u rows r-2..r+2 = ux[e..e+4]
         int rw = r;
         if (IN || wrapc(rw, ny, g.per[1])) {  // wave-uniform
@@ -241,7 +242,7 @@ __device__ __forceinline__ void fwd2d_rows(const FwdArgs<T> &a, int strip, int y
             tlr[0] += e7;
             tlm[0] -= e7;
         }
-        if (e >= 2) {  // output row o = r - 1 (rows y0 .. y0 + RY - 1) is complete
+        if (e >= 2) {  // output row o = r - 1 (rows y0 .. y0 + NR - 1) is complete
             const int o = r - 1;
             const T fr = from_left(trr[0]), fm = from_left(trm[0]);
             const T gr = from_right(tlr[0]), gm = from_right(tlm[0]);
@@ -288,33 +289,62 @@ __device__ __forceinline__ void fwd2d_rows(const FwdArgs<T> &a, int strip, int y
     }
 }
 
-template <typename T>
-__device__ __forceinline__ void fwd2d_body(const FwdArgs<T> &a, int bx, int by, long long slot0) {
-    // the wave index is uniform across a wave: in a scalar register, every per-wave decision below
-    // (strip, interior test, footprint test) is a scalar branch instead of an exec-masked region
-    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const Geom &g = a.g;
+// Work units of one 2D forward step, one per wave, in row bands.  Inner strips (lanes 0..63 inside
+// the grid, no wrap) take RY rows at a time over rows [2, yhi) and run the compiled-out interior
+// variant; every other (strip, row pair) — strips that touch an x face or wrap, and the rows next
+// to the y faces — is a unit of RF rows with the general variant (wraps, one-sided derivatives,
+// boundary pushes), half the height so that those waves take about as long as the interior ones.
+// Unit order: the rows [0, 2) of every strip, then per chunk of RY rows its inner units followed by
+// the outer strips' units on the same rows, then the rows [yhi, ny).  Without inner strips or
+// chunks every unit is general.  Unit k owns objective partial slot k.
+constexpr int RF = 2;
+struct Fwd2dUnits {
+    int nstrips, ninner, nmc, yhi, ngs, band;
+    long long top, mid, total;
+};
+__host__ __device__ inline Fwd2dUnits fwd2d_units(const Geom &g) {
+    Fwd2dUnits u;
     const int nx = g.n[0], ny = g.n[1];
-    const int strip = bx * WPB + w;
-    const long long pslot = slot0 + w;
+    u.nstrips = (nx + SW - 1) / SW;
+    u.nmc = ny >= 4 + RY ? (ny - 4) / RY : 0;
+    u.ninner = (u.nmc > 0 && nx >= 2 * SW + 2) ? (nx - 62) / SW : 0;
+    if (u.ninner == 0) u.nmc = 0;
+    u.ngs = u.nstrips - u.ninner;
+    u.band = u.ninner + (RY / RF) * u.ngs;
+    u.yhi = u.nmc > 0 ? 2 + RY * u.nmc : 0;
+    u.top = u.nmc > 0 ? (long long)u.nstrips : 0;
+    u.mid = (long long)u.nmc * u.band;
+    u.total = u.top + u.mid + (long long)u.nstrips * ((ny - u.yhi + RF - 1) / RF);
+    return u;
+}
+__host__ __device__ inline long long fwd2d_nblocks(const Geom &g) { return (fwd2d_units(g).total + WPB - 1) / WPB; }
+
+template <typename T>
+__device__ __forceinline__ void fwd2d_unit(const FwdArgs<T> &a, const Fwd2dUnits &u, long long k) {
+    const int lane = threadIdx.x & 63;
     const bool obj_on = a.obj.active && a.obj.kind != OBJ_NONE;
-    const int nstrips = (nx + SW - 1) / SW;
-    if (strip >= nstrips) {
-        if (obj_on && lane == 0) gst(a.obj.partials)[pslot] = 0.0;
+    if (k >= u.total) {  // padding wave of the last block
+        if (obj_on && lane == 0) gst(a.obj.partials)[k] = 0.0;
         return;
     }
-    const int y0 = by * RY, cmin = strip * SW - 2;
-    if (cmin >= 0 && cmin + 63 <= nx - 1 && y0 >= 2 && y0 + RY <= ny - 2)
-        fwd2d_rows<T, true>(a, strip, y0, pslot, obj_on);
-    else
-        fwd2d_rows<T, false>(a, strip, y0, pslot, obj_on);
+    int strip, y0;
+    if (k >= u.top && k < u.top + u.mid) {
+        const int kk = (int)(k - u.top);
+        const int c = kk / u.band, m = kk % u.band;
+        if (m < u.ninner) {
+            fwd2d_rows<T, true, RY>(a, 1 + m, 2 + RY * c, k, obj_on);
+            return;
+        }
+        const int gq = m - u.ninner, q = gq % u.ngs;
+        strip = q == 0 ? 0 : u.ninner + q;
+        y0 = 2 + RY * c + RF * (gq / u.ngs);
+    } else {
+        const int kk = (int)(k < u.top ? k : k - u.top - u.mid);
+        strip = kk % u.nstrips;
+        y0 = (k < u.top ? 0 : u.yhi) + RF * (kk / u.nstrips);
+    }
+    fwd2d_rows<T, false, RF>(a, strip, y0, k, obj_on);
 }
-
-__host__ __device__ inline int fwd2d_grid_x(const Geom &g) {
-    const int nstrips = (g.n[0] + SW - 1) / SW;
-    return (nstrips + WPB - 1) / WPB;
-}
-__host__ __device__ inline int fwd2d_grid_y(const Geom &g) { return (g.n[1] + RY - 1) / RY; }
 
 // first tile of the job that owns flat tile b (tile0 ascending, tile0[0] = 0)
 __device__ __forceinline__ int job_of(const long long *tile0, int njobs, long long b) {
@@ -334,14 +364,15 @@ __global__ __launch_bounds__(kBlock) void k_fwd2d_batch(const FwdArgs<T> *__rest
     const int j = __builtin_amdgcn_readfirstlane(job_of(tile0, njobs, b));
     const FwdArgs<T> &a = args[j];
     const long long t = njobs == 1 ? b : b - tile0[j];  // one job: tile0 = {0}
-    const long long ns = (a.mode & FWD_STENCIL) ? (long long)fwd2d_grid_x(a.g) * fwd2d_grid_y(a.g) : 0;
+    const Fwd2dUnits u = fwd2d_units(a.g);
+    const long long ns = (a.mode & FWD_STENCIL) ? (u.total + WPB - 1) / WPB : 0;
     if (t >= ns) {  // extra blocks: transfer of the next step onto its footprint box
         transfer_box<T, 2, kBlock>(a.des, a.mnext, a.box, a.knext, a.usnext, t - ns);
         return;
     }
-    const int nbx = fwd2d_grid_x(a.g);
+    // XCD-aware: each XCD takes a contiguous run of blocks (neighbouring row bands share halos)
     const long long tl = xcd_tile(t, ns);
-    fwd2d_body<T>(a, (int)((unsigned)tl % (unsigned)nbx), (int)((unsigned)tl / (unsigned)nbx), t * WPB);
+    fwd2d_unit<T>(a, u, tl * WPB + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
 }
 
 // transposed difference operator along one axis at coordinate c: sum_r D[r][c] f(r), with f
@@ -886,7 +917,7 @@ __global__ __launch_bounds__(kBlock, LKS_ADJ2D_WAVES) void k_adj2d_batch(const A
 
 long long fwd_blocks(const Geom &g, int lattice, int esz) {
     // one objective partial per wave (2D) or per block (3D)
-    if (g.dim == 2) return (long long)fwd2d_grid_x(g) * fwd2d_grid_y(g) * WPB;
+    if (g.dim == 2) return fwd2d_nblocks(g) * WPB;
     return fwd_blocks3d(g, lattice, esz);
 }
 
@@ -895,7 +926,7 @@ long long xfer_blocks(int dim, long long cells, int esz) {
     return xfer_blocks3d(cells, esz);
 }
 
-long long tiles2d_fwd(const Geom &g) { return (long long)fwd2d_grid_x(g) * fwd2d_grid_y(g); }
+long long tiles2d_fwd(const Geom &g) { return fwd2d_nblocks(g); }
 long long tiles2d(const Geom &g) { return (adj2d_units(g).total + WPB - 1) / WPB; }
 
 template <typename T>
