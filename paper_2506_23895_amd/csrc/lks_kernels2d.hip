@@ -676,18 +676,42 @@ __device__ __forceinline__ void adj2d_rows(const AdjArgs<T> &a, int strip, int y
 // central.  lambda row r = y0 - 2 + j is requested AH rows before it is used; once it arrives it
 // becomes (P*, V*) and its x-stencils, which complete moment row r - 1 (three stencil rows), which
 // completes output row r - 2 (three moment rows).  Each row is loaded and transposed once.
+// XF: the same march for a strip that holds an x face (x not periodic, rows as above).  Its rows
+// meet no y face and wrap nowhere, so the boundary transpose reduces to the single x face: a
+// face node's seed passes to the node next to it (one lane shift, per component as the face's
+// rule copies it), face nodes and columns off the grid hold P* = V* = 0, and the transposed
+// strain uses the one-sided coefficients of the columns next to the face.
 #ifndef LKS_ADJ2D_AHEAD
 #define LKS_ADJ2D_AHEAD 3
 #endif
-template <typename T, int RM, bool WB>
+template <typename T, int RM, bool WB, bool XF>
 __device__ __forceinline__ void adj2d_march(const AdjArgs<T> &a, int strip, int y0) {
     constexpr int NJ = RM + 4;
     constexpr int AH = LKS_ADJ2D_AHEAD;
     const int lane = threadIdx.x & 63;
     const Geom &g = a.g;
+    const int nx = g.n[0];
     const int sy = (int)g.sy;  // grids hold fewer than 2^31 nodes
-    const int c = strip * SWA - 3 + lane;
-    const bool out_lane = lane >= 3 && lane <= 60;
+    const int cr = strip * SWA - 3 + lane;      // this lane's column
+    const int c = XF ? min(max(cr, 0), nx - 1) : cr;  // column it loads from (inside the grid)
+    const bool cval = !XF || cr == c;              // the lane holds a grid column
+    const bool out_lane = lane >= 3 && lane <= 60 && (!XF || cr < nx);
+    // x face: lane next to a face takes that face's seeds, per component as its rule copies them
+    const bool nl = XF && cr == 1, nr = XF && cr == nx - 2, cface = XF && (cr == 0 || cr == nx - 1);
+    const int kl = a.g.per[0] ? 0 : a.bc.kind[0], kr = a.g.per[0] ? 0 : a.bc.kind[1];
+    const bool sl0 = nl && bc_copies(kl, 0, 0), sl1 = nl && bc_copies(kl, 1, 0), sl2 = nl && bc_copies(kl, 2, 0);
+    const bool sr0 = nr && bc_copies(kr, 0, 0), sr1 = nr && bc_copies(kr, 1, 0), sr2 = nr && bc_copies(kr, 2, 0);
+    // transposed x-derivative at this column: sum over o of D[c + o][c] f(c + o), o = -2 .. 2
+    T dco[5];
+    if (XF) {
+        const T fz[5] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+        for (int o = 0; o < 5; ++o) {
+            T f[5] = {fz[0], fz[1], fz[2], fz[3], fz[4]};
+            f[o] = T(1);
+            dco[o] = deriv_T(f, cr, nx, 0);
+        }
+    }
     const bool obj_on = a.obj.active && a.obj.kind != OBJ_NONE;
     const bool kobj = obj_on && obj_uses_kappa(a.obj.kind);
     const bool seeds = obj_on && (WB || !kobj);  // kappa objectives vanish off the footprint
@@ -744,7 +768,7 @@ __device__ __forceinline__ void adj2d_march(const AdjArgs<T> &a, int strip, int 
     for (int j = 0; j < NJ; ++j) {
         const int s = j % AH;
         const int r = y0 - 2 + j;
-        T P = qp[s], Vx = qx[s], Vy = qy[s];
+        T P = cval ? qp[s] : T(0), Vx = cval ? qx[s] : T(0), Vy = cval ? qy[s] : T(0);
         const bool inb = WB && in_box(a.m, 2, c, r, 0);
         const T kap = inb ? qk[s] : T(0), usx = inb ? qs0[s] : T(0), usy = inb ? qs1[s] : T(0);
         const T ucx = inb ? qc0[s] : T(0), ucy = inb ? qc1[s] : T(0);
@@ -754,13 +778,21 @@ __device__ __forceinline__ void adj2d_march(const AdjArgs<T> &a, int strip, int 
         if (j + AH < NJ) issue(j + AH);
 
         // lambda + dj/dX, then the force transpose
-        if (seeds && mk && !(kobj && kap == T(0))) {
+        if (seeds && cval && mk && !(kobj && kap == T(0))) {
             const double us[3] = {(double)usx, (double)usy, 0.0};
             double dP, dV[3];
             obj_dstate(a.obj, c, r, 0, (double)kap, us, dP, dV);
             P += (T)(sc * dP);
             Vx += (T)(sc * dV[0]);
             Vy += (T)(sc * dV[1]);
+        }
+        if (XF) {  // boundary transpose of the x face
+            const T pL = from_left(P), xL = from_left(Vx), yL = from_left(Vy);
+            const T pR = from_right(P), xR = from_right(Vx), yR = from_right(Vy);
+            P += (sl0 ? pL : T(0)) + (sr0 ? pR : T(0));
+            Vx += (sl1 ? xL : T(0)) + (sr1 ? xR : T(0));
+            Vy += (sl2 ? yL : T(0)) + (sr2 ? yR : T(0));
+            if (cface || !cval) P = Vx = Vy = T(0);
         }
         if (brink) {
             const T inv = rcp_t(T(1) + kap + ks);
@@ -815,8 +847,14 @@ __device__ __forceinline__ void adj2d_march(const AdjArgs<T> &a, int strip, int 
             const T *mm = mo[(j - 3) % 3], *m0 = mo[(j - 2) % 3], *mp = mo[(j - 1) % 3];
             const T xxl = from_left(m0[3]), xxr = from_right(m0[3]);
             const T xyl = from_left(m0[4]), xyr = from_right(m0[4]);
-            const T dxx = T(0.5) * (xxl - xxr);
-            const T dxy = T(0.5) * (xyl - xyr);
+            T dxx, dxy;
+            if (XF) {
+                dxx = dco[0] * from_left(xxl) + dco[1] * xxl + dco[2] * m0[3] + dco[3] * xxr + dco[4] * from_right(xxr);
+                dxy = dco[0] * from_left(xyl) + dco[1] * xyl + dco[2] * m0[4] + dco[3] * xyr + dco[4] * from_right(xyr);
+            } else {
+                dxx = T(0.5) * (xxl - xxr);
+                dxy = T(0.5) * (xyl - xyr);
+            }
             const T dyxy = T(0.5) * (mm[4] - mp[4]);
             const T dyyy = T(0.5) * (mm[5] - mp[5]);
             const T rt = m0[0];
@@ -836,17 +874,19 @@ __device__ __forceinline__ void adj2d_march(const AdjArgs<T> &a, int strip, int 
     }
 }
 
-// Work units of one 2D adjoint step, one per wave.  Inner strips (every lane's column at least one
-// node off the x faces, no wrap) march RMA rows at a time over rows [4, yhi); every other
-// (strip, row pair) — strips that touch an x face or wrap, and the four rows next to each y face or
-// wrap — is a general unit of RGA rows with the full boundary transpose.  March units come first,
-// then general units of the outer strips, then the y-edge units of the inner strips.
+// Work units of one 2D adjoint step, one per wave.  Over rows [4, yhi), in chunks of RMA rows,
+// every strip marches: inner strips (every lane's column at least one node off the x faces, no
+// wrap) with the interior variant, the outer strips that hold an x face with the XF variant (x not
+// periodic).  Everything else — the four rows next to each y face (or the wrap of a periodic y),
+// and all rows of the outer strips when x is periodic — is a general unit of RGA rows with the
+// full boundary transpose.  March units come first (they are the longest), then the outer strips'
+// general units, then the y-edge units of the marching strips.
 #ifndef LKS_ADJ2D_RM
 #define LKS_ADJ2D_RM 8
 #endif
 constexpr int RMA = LKS_ADJ2D_RM;
 struct Adj2dUnits {
-    int nstrips, ninner, nmc, yhi, ngs, ngr, neg;
+    int nstrips, ninner, nms, nmc, yhi, ngs, ngr, neg;
     long long nmarch, nouter, total;
 };
 __host__ __device__ inline Adj2dUnits adj2d_units(const Geom &g) {
@@ -858,27 +898,39 @@ __host__ __device__ inline Adj2dUnits adj2d_units(const Geom &g) {
     if (u.ninner == 0) u.nmc = 0;
     u.yhi = 4 + RMA * u.nmc;
     u.ngs = u.nstrips - u.ninner;
+    u.nms = u.ninner + ((u.nmc > 0 && !g.per[0]) ? u.ngs : 0);  // marching strips
     u.ngr = (ny + RGA - 1) / RGA;
-    u.neg = u.ninner > 0 ? 2 + (ny - u.yhi + RGA - 1) / RGA : 0;
-    u.nmarch = (long long)u.ninner * u.nmc;
-    u.nouter = (long long)u.ngs * u.ngr;
-    u.total = u.nmarch + u.nouter + (long long)u.ninner * u.neg;
+    u.neg = u.nms > 0 ? 2 + (ny - u.yhi + RGA - 1) / RGA : 0;
+    u.nmarch = (long long)u.nms * u.nmc;
+    u.nouter = u.nms > u.ninner ? 0 : (long long)u.ngs * u.ngr;
+    u.total = u.nmarch + u.nouter + (long long)u.nms * u.neg;
     return u;
+}
+
+// strip of marching-strip index i: inner strips 1 .. ninner, then the outer ones
+__host__ __device__ inline int adj2d_mstrip(const Adj2dUnits &u, int i) {
+    return i < u.ninner ? 1 + i : (i == u.ninner ? 0 : i);
 }
 
 template <typename T>
 __device__ __forceinline__ void adj2d_unit(const AdjArgs<T> &a, const Adj2dUnits &u, long long k) {
+    int strip, y0;
     if (k < u.nmarch) {
-        const int kk = (int)k;
-        const int strip = 1 + kk % u.ninner, y0 = 4 + RMA * (kk / u.ninner);
+        const int kk = (int)k, i = kk % u.nms;
+        strip = adj2d_mstrip(u, i);
+        y0 = 4 + RMA * (kk / u.nms);
         const int cmin = strip * SWA - 3;
         const bool wbox = a.m.hi[0] >= cmin && a.m.lo[0] <= cmin + 63 && a.m.hi[1] >= y0 - 2 &&
                           a.m.lo[1] <= y0 + RMA + 1;
-        if (wbox) adj2d_march<T, RMA, true>(a, strip, y0);
-        else adj2d_march<T, RMA, false>(a, strip, y0);
+        if (i < u.ninner) {
+            if (wbox) adj2d_march<T, RMA, true, false>(a, strip, y0);
+            else adj2d_march<T, RMA, false, false>(a, strip, y0);
+        } else {
+            if (wbox) adj2d_march<T, RMA, true, true>(a, strip, y0);
+            else adj2d_march<T, RMA, false, true>(a, strip, y0);
+        }
         return;
     }
-    int strip, y0;
     if (k < u.nmarch + u.nouter) {
         const int v = (int)(k - u.nmarch);
         const int q = v % u.ngs;
@@ -886,8 +938,8 @@ __device__ __forceinline__ void adj2d_unit(const AdjArgs<T> &a, const Adj2dUnits
         y0 = RGA * (v / u.ngs);
     } else {
         const int v = (int)(k - u.nmarch - u.nouter);
-        const int q = v / u.ninner;
-        strip = 1 + v % u.ninner;
+        const int q = v / u.nms;
+        strip = adj2d_mstrip(u, v % u.nms);
         y0 = q < 2 ? RGA * q : u.yhi + RGA * (q - 2);
     }
     adj2d_rows<T, false, RGA>(a, strip, y0);
