@@ -333,9 +333,20 @@ __device__ __forceinline__ void fwd3d_body(const FwdArgs<T> &a, int bx, int by, 
                     (void)dummy;
                     if (opp<Q>(q) < q) continue;
                     const int cx = cq<Q>(q, 0), cy = cq<Q>(q, 1), cz = cq<Q>(q, 2);
-                    T ev = a0 + T(cx * cx) * tt[0][0] + T(cy * cy) * tt[1][1] + T(cz * cz) * tt[2][2];
-                    ev += T(2 * cx * cy) * tt[0][1] + T(2 * cx * cz) * tt[0][2] + T(2 * cy * cz) * tt[1][2];
-                    const T od = T(3) * (T(cx) * u[0] + T(cy) * u[1] + T(cz) * u[2]);
+                    // c.T.c and c.u over the non-zero components of c only (|c_b| <= 1): a product
+                    // with a zero coefficient is not folded away in IEEE arithmetic
+                    T ev = a0;
+                    if (cx) ev += tt[0][0];
+                    if (cy) ev += tt[1][1];
+                    if (cz) ev += tt[2][2];
+                    if (cx && cy) ev += T(2 * cx * cy) * tt[0][1];
+                    if (cx && cz) ev += T(2 * cx * cz) * tt[0][2];
+                    if (cy && cz) ev += T(2 * cy * cz) * tt[1][2];
+                    T cu = T(0);
+                    if (cx) cu += T(cx) * u[0];
+                    if (cy) cu += T(cy) * u[1];
+                    if (cz) cu += T(cz) * u[2];
+                    const T od = T(3) * cu;
                     sE[q - 1][i] = T(wq<Q>(q)) * (ev + od);
                     sE[opp<Q>(q) - 1][i] = T(wq<Q>(q)) * (ev - od);
                 }
@@ -646,19 +657,23 @@ __device__ __forceinline__ void adj3d_main_body(const AdjArgs<T> &a, int bx, int
             const int cx = cq<Q>(q, 0), cy = cq<Q>(q, 1), cz = cq<Q>(q, 2);
             const int sl = ring3(zm + cz);
             const int pi = (ly + 1 + cy) * PX + (lx + 1 + cx);
-            const T eb = spv[sl][0][pi] + T(cx) * spv[sl][1][pi] + T(cy) * spv[sl][2][pi] +
-                         T(cz) * spv[sl][3][pi];
+            // only the non-zero components of c (|c_b| <= 1) contribute: a product with a zero
+            // coefficient is not folded away in IEEE arithmetic, and its LDS read is skipped too
+            T eb = spv[sl][0][pi];
+            if (cx) eb += T(cx) * spv[sl][1][pi];
+            if (cy) eb += T(cy) * spv[sl][2][pi];
+            if (cz) eb += T(cz) * spv[sl][3][pi];
             const T we = T(wq<Q>(q)) * eb;
-            m[0] += we;                // rho~
-            m[1] += T(cx) * we;        // u~
-            m[2] += T(cy) * we;
-            m[3] += T(cz) * we;
-            m[4] += T(cx * cx) * we;   // s~ xx, yy, zz, xy, xz, yz
-            m[5] += T(cy * cy) * we;
-            m[6] += T(cz * cz) * we;
-            m[7] += T(cx * cy) * we;
-            m[8] += T(cx * cz) * we;
-            m[9] += T(cy * cz) * we;
+            m[0] += we;                            // rho~
+            if (cx) m[1] += T(cx) * we;            // u~
+            if (cy) m[2] += T(cy) * we;
+            if (cz) m[3] += T(cz) * we;
+            if (cx) m[4] += we;                    // s~ xx, yy, zz, xy, xz, yz
+            if (cy) m[5] += we;
+            if (cz) m[6] += we;
+            if (cx && cy) m[7] += T(cx * cy) * we;
+            if (cx && cz) m[8] += T(cx * cz) * we;
+            if (cy && cz) m[9] += T(cy * cz) * we;
         }
     };
 
