@@ -22,6 +22,23 @@ __device__ __forceinline__ const LKS_GLOBAL T *gld(const T *p) { return (const L
 template <typename T>
 __device__ __forceinline__ LKS_GLOBAL T *gst(T *p) { return (LKS_GLOBAL T *)p; }
 
+// ---- lane shifts within a 64-wide wavefront (DPP wave_shr:1 / wave_shl:1; edge lanes read 0) ----
+__device__ __forceinline__ int dpp_l(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, true); }
+__device__ __forceinline__ int dpp_r(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, true); }
+// value of lane i-1 / lane i+1
+__device__ __forceinline__ float from_left(float v) { return __builtin_bit_cast(float, dpp_l(__builtin_bit_cast(int, v))); }
+__device__ __forceinline__ float from_right(float v) { return __builtin_bit_cast(float, dpp_r(__builtin_bit_cast(int, v))); }
+__device__ __forceinline__ double from_left(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = dpp_l((int)(b & 0xffffffffLL)), hi = dpp_l((int)(b >> 32));
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double from_right(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = dpp_r((int)(b & 0xffffffffLL)), hi = dpp_r((int)(b >> 32));
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
 // wrap a coordinate onto a periodic axis; false if it leaves a non-periodic axis
 __device__ __forceinline__ bool wrapc(int &v, int n, int per) {
     if (v >= 0 && v < n) return true;

@@ -33,23 +33,6 @@ __device__ constexpr int cy(int i) {
 __device__ constexpr double wt(int i) { return i == 0 ? W0 : (i < 5 ? WA : WD); }
 }  // namespace d2q9
 
-// ---- lane shifts within a 64-wide wavefront (DPP wave_shr:1 / wave_shl:1; edge lanes read 0) ----
-__device__ __forceinline__ int dpp_l(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, true); }
-__device__ __forceinline__ int dpp_r(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, true); }
-// value of lane i-1 / lane i+1
-__device__ __forceinline__ float from_left(float v) { return __builtin_bit_cast(float, dpp_l(__builtin_bit_cast(int, v))); }
-__device__ __forceinline__ float from_right(float v) { return __builtin_bit_cast(float, dpp_r(__builtin_bit_cast(int, v))); }
-__device__ __forceinline__ double from_left(double v) {
-    const long long b = __builtin_bit_cast(long long, v);
-    const int lo = dpp_l((int)(b & 0xffffffffLL)), hi = dpp_l((int)(b >> 32));
-    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ __forceinline__ double from_right(double v) {
-    const long long b = __builtin_bit_cast(long long, v);
-    const int lo = dpp_r((int)(b & 0xffffffffLL)), hi = dpp_r((int)(b >> 32));
-    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
-}
-
 // Forward step as wave strips marching along y.  Lane l of wave w holds column
 // c = 60 * strip - 2 + l; lanes 2..61 produce outputs, lanes 0, 1, 62, 63 are the column halo.
 // A wave owns NR output rows (RY in the interior, RF next to faces): it issues the loads of every

@@ -496,10 +496,106 @@ __device__ __forceinline__ void lambda_at(const AdjArgs<T> &a, int x, int y, int
     lam[3] += (T)(sc * dV[2]);
 }
 
+// Row fast path of the pointwise part: the wave's 64 nodes are consecutive in x within one (y, z)
+// row that is neither on nor next to a non-periodic y or z face.  The only boundary rule that can
+// reach them is an x face inside the wave: face nodes hold P* = V* = 0 and the node next to a face
+// takes that face's seed through one lane shift, per component as the face's rule copies it
+// (the wave holds the face whenever it holds the node next to it; the caller checks).
+template <typename T>
+__device__ __forceinline__ void adj3d_prep_row(const AdjArgs<T> &a, int x0, int y, int z) {
+    const Geom &g = a.g;
+    const int lane = threadIdx.x & 63;
+    const int x = x0 + lane, nx = g.n[0];
+    const long long idx = x + y * g.sy + z * g.sz;
+    T lam[4] = {a.Pin[idx], a.Vin[0][idx], a.Vin[1][idx], a.Vin[2][idx]};
+    // footprint values of the row: one clamped load per lane when the row meets the box
+    const bool rbox = y >= a.m.lo[1] && y <= a.m.hi[1] && z >= a.m.lo[2] && z <= a.m.hi[2] &&
+                      a.m.hi[0] >= x0 && a.m.lo[0] <= x0 + 63;
+    const bool inb = rbox && x >= a.m.lo[0] && x <= a.m.hi[0];
+    T kap = T(0), us[3] = {T(0), T(0), T(0)}, uc[3] = {T(0), T(0), T(0)};
+    long long bi = 0;
+    if (rbox) {  // wave-uniform
+        const int xc = min(max(x, a.m.lo[0]), a.m.hi[0]);
+        bi = box_index(a.box, a.m, 3, xc, y, z);
+        const long long ic = xc + y * g.sy + z * g.sz;  // a box node: inside the grid
+        const T k0 = a.kbox[bi], s0 = a.usbox[0][bi], s1 = a.usbox[1][bi], s2 = a.usbox[2][bi];
+        const T c0 = a.ucur[0][ic], c1 = a.ucur[1][ic], c2 = a.ucur[2][ic];
+        kap = inb ? k0 : T(0);
+        us[0] = inb ? s0 : T(0);
+        us[1] = inb ? s1 : T(0);
+        us[2] = inb ? s2 : T(0);
+        uc[0] = c0;
+        uc[1] = c1;
+        uc[2] = c2;
+    }
+    const bool obj_on = a.obj.active && a.obj.kind != OBJ_NONE;
+    const bool kobj = obj_on && obj_uses_kappa(a.obj.kind);
+    if (obj_on && (rbox || !kobj)) {  // kappa objectives vanish off the footprint
+        const bool mk = !a.obj.mask || a.obj.mask[idx];
+        if (mk && !(kobj && kap == T(0))) {
+            const double usd[3] = {(double)us[0], (double)us[1], (double)us[2]};
+            double dP, dV[3];
+            obj_dstate(a.obj, x, y, z, (double)kap, usd, dP, dV);
+            const double sc = a.obj.scale;
+            lam[0] += (T)(sc * dP);
+            lam[1] += (T)(sc * dV[0]);
+            lam[2] += (T)(sc * dV[1]);
+            lam[3] += (T)(sc * dV[2]);
+        }
+    }
+    if (!g.per[0]) {  // the x faces
+        const int kl = a.bc.kind[0], kr = a.bc.kind[1];
+        const bool nl = x == 1, nr = x == nx - 2;
+        T sh[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const T fl = from_left(lam[c]), fr = from_right(lam[c]);
+            sh[c] = (nl && bc_copies(kl, c, 0) ? fl : T(0)) + (nr && bc_copies(kr, c, 0) ? fr : T(0));
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) lam[c] += sh[c];
+        if (x == 0 || x == nx - 1) lam[0] = lam[1] = lam[2] = lam[3] = T(0);
+    }
+    const T ks = a.kstatic ? a.kstatic[idx] : T(0);
+    const T inv = T(1) / (T(1) + kap + ks);
+    const T V[3] = {lam[1] * inv, lam[2] * inv, lam[3] * inv};
+    a.Ps[idx] = lam[0];
+    a.Vs[0][idx] = V[0];
+    a.Vs[1][idx] = V[1];
+    a.Vs[2][idx] = V[2];
+    if (inb) {
+        double uu[3], uss[3];
+        double kb = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            uu[k] = (double)uc[k];
+            uss[k] = (double)us[k];
+            kb -= (double)V[k] * (uu[k] - uss[k]);
+        }
+        if (kobj && (!a.obj.mask || a.obj.mask[idx]))
+            kb += a.obj.scale * obj_dkappa(a.obj, x, y, z, uu, uss);
+        a.kbar[bi] = (T)kb;
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ void adj3d_prep_body(const AdjArgs<T> &a, long long blk) {
     const Geom &g = a.g;
     const long long ncell = (long long)g.n[0] * g.n[1] * g.n[2];
+    {   // wave-uniform row test for the fast path
+        const long long tw = blk * kBlock + 64 * __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        const unsigned twu = (unsigned)tw, n0 = (unsigned)g.n[0], n1 = (unsigned)g.n[1];
+        const int x0 = (int)(twu % n0), y = (int)((twu / n0) % n1), z = (int)(twu / (n0 * n1));
+        const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+        const bool row = tw + 63 < ncell && x0 + 63 < nx;
+        const bool yok = g.per[1] || (y >= 2 && y <= ny - 3);
+        const bool zok = g.per[2] || (z >= 2 && z <= nz - 3);
+        const bool xok = g.per[0] || (x0 != 1 && x0 + 63 != nx - 2);  // a face next to the wave's ends
+        if (row && yok && zok && xok) {
+            adj3d_prep_row<T>(a, x0, y, z);
+            return;
+        }
+    }
     const long long t = blk * kBlock + threadIdx.x;
     if (t >= ncell) return;
     const unsigned tu = (unsigned)t, n0 = (unsigned)g.n[0], n1 = (unsigned)g.n[1];  // < 2^31 cells
