@@ -76,18 +76,24 @@ __device__ __forceinline__ double rcp_t(double v) { return 1.0 / v; }
 // IN: the wave touches no face, needs no periodic wrap and every E row it evaluates has central
 // differences on both axes (decided per wave), so the bounds, wrap, one-sided and boundary-push
 // code is compiled out.
-template <typename T, bool IN, int NR>
+template <typename T, bool IN, int NR, bool XF = false>
 __device__ __forceinline__ void fwd2d_rows(const FwdArgs<T> &a, int strip, int y0, long long pslot,
                                            bool obj_on) {
     const int lane = threadIdx.x & 63;
     const Geom &g = a.g;
     const int nx = g.n[0], ny = g.n[1];
     const int c = strip * SW - 2 + lane;
+    // XF (with IN): a strip that holds an x face, x not periodic, rows as IN.  Loads come from the
+    // clamped column, columns off the grid contribute nothing, the face columns take one-sided
+    // x-derivatives, and the lane next to a face writes the face node by that face's rule.
+    const int cl = XF ? min(max(c, 0), nx - 1) : c;
+    const bool cval = !XF || cl == c;
     int cw = c;
-    const bool cin = IN || wrapc(cw, nx, g.per[0]);
+    const bool cin = IN ? cval : wrapc(cw, nx, g.per[0]);
     const int cmin = strip * SW - 2, cmax = cmin + 63;
     const bool xface = !IN && !g.per[0] && ((cmin <= 0 && 0 <= cmax) || (cmin <= nx - 1 && nx - 1 <= cmax));
-    const bool out_lane = lane >= 2 && lane < 62 && (IN || (c < nx && !on_face(g, 0, c)));
+    const bool out_lane = lane >= 2 && lane < 62 &&
+                          (IN ? (!XF || (cval && c != 0 && c != nx - 1)) : (c < nx && !on_face(g, 0, c)));
     const LKS_GLOBAL T *__restrict__ ux_in = gld(a.uin[0]);
     const LKS_GLOBAL T *__restrict__ uy_in = gld(a.uin[1]);
     const LKS_GLOBAL T *__restrict__ r_in = gld(a.rin);
@@ -110,9 +116,10 @@ __device__ __forceinline__ void fwd2d_rows(const FwdArgs<T> &a, int strip, int y
         ux[k] = uy[k] = T(0);
         if (IN) {
             if (k == 0) continue;  // the one-sided stencils that read row y0 - 3 never run here
-            const long long idx = c + (long long)yw * g.sy;
-            ux[k] = ux_in[idx];
-            uy[k] = uy_in[idx];
+            const long long idx = cl + (long long)yw * g.sy;
+            const T v0 = ux_in[idx], v1 = uy_in[idx];
+            ux[k] = cval ? v0 : T(0);
+            uy[k] = cval ? v1 : T(0);
         } else {
             const bool ok = cin && wrapc(yw, ny, g.per[1]);
             const long long idx = ok ? cw + (long long)yw * g.sy : 0;
@@ -126,7 +133,8 @@ __device__ __forceinline__ void fwd2d_rows(const FwdArgs<T> &a, int strip, int y
         int yw = y0 - 1 + k;
         rv[k] = T(0);
         if (IN) {
-            rv[k] = r_in[c + (long long)yw * g.sy];
+            const T v = r_in[cl + (long long)yw * g.sy];
+            rv[k] = cval ? v : T(0);
         } else {
             const bool ok = cin && wrapc(yw, ny, g.per[1]);
             const T v = r_in[ok ? cw + (long long)yw * g.sy : 0];
@@ -174,7 +182,7 @@ __device__ __forceinline__ void fwd2d_rows(const FwdArgs<T> &a, int strip, int y
             const T uyl = from_left(uyc), uyr = from_right(uyc);
             // twice the derivatives: central (f+ - f-), one-sided 2 (-1.5 f0 + 2 f1 - 0.5 f2)
             T gxux = uxr - uxl, gxuy = uyr - uyl;
-            if (!IN && xface) {
+            if ((!IN && xface) || XF) {
                 const T uxll = from_left(uxl), uxrr = from_right(uxr);
                 const T uyll = from_left(uyl), uyrr = from_right(uyr);
                 if (c == 0) {
@@ -199,13 +207,13 @@ __device__ __forceinline__ void fwd2d_rows(const FwdArgs<T> &a, int strip, int y
             const T tyy = T(4.5) * uyc * uyc + A * gyuy;
             const T txy2 = T(9) * uxc * uyc + A * (gyux + gxuy);
             const T q = a0 + txx + tyy;
-            const T m = (IN || cin) ? T(1) : T(0);  // nothing from columns outside the domain
+            const T m = cin ? T(1) : T(0);  // nothing from columns outside the domain
             T e0 = w0 * a0;
             T e1 = wa * (a0 + bx3 + txx), e3 = wa * (a0 - bx3 + txx);
             T e2 = wa * (a0 + by3 + tyy), e4 = wa * (a0 - by3 + tyy);
             T e5 = wd * (q + bx3 + by3 + txy2), e6 = wd * (q - bx3 + by3 - txy2);
             T e7 = wd * (q - bx3 - by3 + txy2), e8 = wd * (q + bx3 - by3 - txy2);
-            if (!IN) {
+            if (!IN || XF) {
                 e0 *= m; e1 *= m; e2 *= m; e3 *= m; e4 *= m;
                 e5 *= m; e6 *= m; e7 *= m; e8 *= m;
             }
@@ -250,6 +258,20 @@ __device__ __forceinline__ void fwd2d_rows(const FwdArgs<T> &a, int strip, int y
                 }
                 if (!IN && (c == 1 || c == nx - 2 || o == 1 || o == ny - 2))
                     jacc += fwd2d_push<T>(a, c, o, rs, nux, nuy, obj_on);
+                if (XF && (c == 1 || c == nx - 2)) {  // the face node next to this one
+                    const int f = c == 1 ? 0 : 1, kind = a.bc.kind[f], pc = c == 1 ? 0 : nx - 1;
+                    const T pr = bc_copies(kind, 0, 0) ? rs : a.bc.rho[f];
+                    const T pux = bc_copies(kind, 1, 0) ? nux : a.bc.u[f][0];
+                    const T puy = bc_copies(kind, 2, 0) ? nuy : a.bc.u[f][1];
+                    const long long pi = pc + (long long)o * g.sy;
+                    r_out[pi] = pr;
+                    ux_out[pi] = pux;
+                    uy_out[pi] = puy;
+                    if (obj_on && !obj_uses_kappa(a.obj.kind) && (!omask || omask[pi])) {
+                        const T pu[3] = {pux, puy, T(0)}, z3[3] = {T(0), T(0), T(0)};
+                        jacc += obj_density<T>(a.obj, pc, o, 0, (double)pr, pu, T(0), z3);
+                    }
+                }
             }
         }
         acc_r[0] = acc_r[1]; acc_r[1] = acc_r[2]; acc_r[2] = T(0);
@@ -272,17 +294,18 @@ __device__ __forceinline__ void fwd2d_rows(const FwdArgs<T> &a, int strip, int y
     }
 }
 
-// Work units of one 2D forward step, one per wave, in row bands.  Inner strips (lanes 0..63 inside
-// the grid, no wrap) take RY rows at a time over rows [2, yhi) and run the compiled-out interior
-// variant; every other (strip, row pair) — strips that touch an x face or wrap, and the rows next
-// to the y faces — is a unit of RF rows with the general variant (wraps, one-sided derivatives,
-// boundary pushes), half the height so that those waves take about as long as the interior ones.
-// Unit order: the rows [0, 2) of every strip, then per chunk of RY rows its inner units followed by
-// the outer strips' units on the same rows, then the rows [yhi, ny).  Without inner strips or
-// chunks every unit is general.  Unit k owns objective partial slot k.
+// Work units of one 2D forward step, one per wave, in row bands.  Over rows [2, yhi), in chunks of
+// RY rows, every strip is one unit: inner strips (lanes 0..63 inside the grid, no wrap) with the
+// compiled-out interior variant, outer strips that hold an x face (x not periodic) with the XF
+// variant.  Every other (strip, row pair) — the rows next to the y faces (or a periodic y's wrap),
+// and all rows of the outer strips when x is periodic — is a unit of RF rows with the general
+// variant (wraps, one-sided derivatives, composite boundary pushes), half the height so that those
+// waves take about as long as the others.  Unit order: the rows [0, 2) of every strip, then per
+// chunk its units (inner strips, then outer ones), then the rows [yhi, ny).  Without inner strips
+// or chunks every unit is general.  Unit k owns objective partial slot k.
 constexpr int RF = 2;
 struct Fwd2dUnits {
-    int nstrips, ninner, nmc, yhi, ngs, band;
+    int nstrips, ninner, nmc, yhi, ngs, nxf, band;
     long long top, mid, total;
 };
 __host__ __device__ inline Fwd2dUnits fwd2d_units(const Geom &g) {
@@ -293,7 +316,8 @@ __host__ __device__ inline Fwd2dUnits fwd2d_units(const Geom &g) {
     u.ninner = (u.nmc > 0 && nx >= 2 * SW + 2) ? (nx - 62) / SW : 0;
     if (u.ninner == 0) u.nmc = 0;
     u.ngs = u.nstrips - u.ninner;
-    u.band = u.ninner + (RY / RF) * u.ngs;
+    u.nxf = g.per[0] ? 0 : u.ngs;  // outer strips with an XF unit per chunk
+    u.band = u.ninner + (u.nxf > 0 ? u.nxf : (RY / RF) * u.ngs);
     u.yhi = u.nmc > 0 ? 2 + RY * u.nmc : 0;
     u.top = u.nmc > 0 ? (long long)u.nstrips : 0;
     u.mid = (long long)u.nmc * u.band;
@@ -318,7 +342,12 @@ __device__ __forceinline__ void fwd2d_unit(const FwdArgs<T> &a, const Fwd2dUnits
             fwd2d_rows<T, true, RY>(a, 1 + m, 2 + RY * c, k, obj_on);
             return;
         }
-        const int gq = m - u.ninner, q = gq % u.ngs;
+        const int gq = m - u.ninner;
+        if (u.nxf > 0) {
+            fwd2d_rows<T, true, RY, true>(a, gq == 0 ? 0 : u.ninner + gq, 2 + RY * c, k, obj_on);
+            return;
+        }
+        const int q = gq % u.ngs;
         strip = q == 0 ? 0 : u.ninner + q;
         y0 = 2 + RY * c + RF * (gq / u.ngs);
     } else {
