@@ -394,8 +394,26 @@ __device__ __forceinline__ void fwd3d_body(const FwdArgs<T> &a, int bx, int by, 
                 jacc += obj_density<T>(a.obj, gxo, gyo, zo, (double)rs, nu, kap, us);
             }
             const bool zadj = !per2 && (zo == 1 || zo == nz - 2);
-            if ((xface && (gxo == 1 || gxo == nx - 2)) || (yface && (gyo == 1 || gyo == ny - 2)) || zadj)
+            if (xface && !yface && !zadj) {  // block- and plane-uniform: only an x face is in reach
+                if (gxo == 1 || gxo == nx - 2) {  // the face node next to this one, by that face's rule
+                    const int f = gxo == 1 ? 0 : 1, kind = a.bc.kind[f], pc = gxo == 1 ? 0 : nx - 1;
+                    const T pr = bc_copies(kind, 0, 0) ? rs : a.bc.rho[f];
+                    const T p0 = bc_copies(kind, 1, 0) ? nu0 : a.bc.u[f][0];
+                    const T p1 = bc_copies(kind, 2, 0) ? nu1 : a.bc.u[f][1];
+                    const T p2 = bc_copies(kind, 3, 0) ? nu2 : a.bc.u[f][2];
+                    const long long pi = pc + (long long)gyo * g.sy + (long long)zo * sz;
+                    rout[pi] = pr;
+                    uout0[pi] = p0;
+                    uout1[pi] = p1;
+                    uout2[pi] = p2;
+                    if (obj_on && !kobj && (!omask || omask[pi])) {
+                        const T pu[3] = {p0, p1, p2}, z3[3] = {T(0), T(0), T(0)};
+                        jacc += obj_density<T>(a.obj, pc, gyo, zo, (double)pr, pu, T(0), z3);
+                    }
+                }
+            } else if ((xface && (gxo == 1 || gxo == nx - 2)) || (yface && (gyo == 1 || gyo == ny - 2)) || zadj) {
                 jacc += fwd3d_push<T>(a, gxo, gyo, zo, rs, nu0, nu1, nu2, obj_on);
+            }
         }
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
