@@ -108,6 +108,18 @@ WIDE_CASES["static_solid_force"] = dict(obj="POWER", kappa_static=_static_solid(
                                         body_force=(2e-6, -1e-6, 0.0))
 
 
+# Widths that put a right x face at the edge lanes of a face strip: 180 puts it at lane 61 of the
+# forward's last strip (output lanes 2..61), 232 at lane 60 of the adjoint's (output lanes 3..60).
+@pytest.mark.parametrize("nx", [180, 232])
+@pytest.mark.parametrize("obj", ["DRAG", "J2"])
+def test_face_lane_edges_fp64(nx, obj):
+    cfg = small(n=(nx, 40), nd=(20, 16), N=30, K=8, obj=obj,
+                bcs=[_bc("VELOCITY", 1.0, (0.03, 0, 0)), _bc("PRESSURE", 1.001, (0, 0.003, 0)),
+                     _bc("NOSLIP"), _bc("NOSLIP", 1.0, (0.01, 0, 0)), _bc("PERIODIC"), _bc("PERIODIC")])
+    announce(f"face lane edges nx={nx} {obj}")
+    compare(cfg, I.gamma_field(cfg["nd"], 2, 9), **F64)
+
+
 @pytest.mark.parametrize("name", sorted(WIDE_CASES))
 def test_variants_wide_fp64(name):
     kw = dict(WIDE_CASES[name])
