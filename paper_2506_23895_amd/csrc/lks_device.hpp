@@ -353,6 +353,51 @@ __device__ __forceinline__ double obj_dkappa(const ObjParams &o, int x, int y, i
     return 0.0;
 }
 
+// The same two partials in the arithmetic type R of the caller (R = double reproduces the two
+// functions above operation for operation).
+template <typename R>
+__device__ __forceinline__ void obj_dstate_r(const ObjParams &o, int x, int y, int z, R kap, const R us[3],
+                                             R &dP, R dV[3]) {
+    dP = R(0);
+    dV[0] = dV[1] = dV[2] = R(0);
+    switch (o.kind) {
+    case OBJ_DRAG:
+        for (int a = 0; a < 3; ++a) dV[a] = kap * (R)o.dir[a];
+        break;
+    case OBJ_POWER:
+        for (int a = 0; a < 3; ++a) dV[a] = kap * us[a];
+        break;
+    case OBJ_TORQUE: {
+        const R r0 = (R)(x - o.centre[0]), r1 = (R)(y - o.centre[1]), r2 = (R)(z - o.centre[2]);
+        dV[0] = kap * ((R)o.dir[1] * r2 - (R)o.dir[2] * r1);
+        dV[1] = kap * ((R)o.dir[2] * r0 - (R)o.dir[0] * r2);
+        dV[2] = kap * ((R)o.dir[0] * r1 - (R)o.dir[1] * r0);
+        break;
+    }
+    case OBJ_J1: dP = R(-1.0 / 3.0); break;
+    case OBJ_J2:
+        for (int a = 0; a < 3; ++a) dV[a] = -(R)o.dir[a];
+        break;
+    case OBJ_MASS: dP = R(1); break;
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ R obj_dkappa_r(const ObjParams &o, int x, int y, int z, const R u[3], const R us[3]) {
+    const R v0 = u[0] - us[0], v1 = u[1] - us[1], v2 = u[2] - us[2];
+    switch (o.kind) {
+    case OBJ_DRAG: return v0 * (R)o.dir[0] + v1 * (R)o.dir[1] + v2 * (R)o.dir[2];
+    case OBJ_POWER: return v0 * us[0] + v1 * us[1] + v2 * us[2];
+    case OBJ_TORQUE: {
+        const R r0 = (R)(x - o.centre[0]), r1 = (R)(y - o.centre[1]), r2 = (R)(z - o.centre[2]);
+        const R m0 = (R)o.dir[1] * r2 - (R)o.dir[2] * r1, m1 = (R)o.dir[2] * r0 - (R)o.dir[0] * r2,
+                m2 = (R)o.dir[0] * r1 - (R)o.dir[1] * r0;
+        return v0 * m0 + v1 * m1 + v2 * m2;
+    }
+    }
+    return R(0);
+}
+
 __device__ __forceinline__ bool obj_uses_kappa(int kind) {
     return kind == OBJ_DRAG || kind == OBJ_POWER || kind == OBJ_TORQUE;
 }

@@ -727,7 +727,7 @@ __device__ __forceinline__ void adj2d_march(const AdjArgs<T> &a, int strip, int 
     const bool obj_on = a.obj.active && a.obj.kind != OBJ_NONE;
     const bool kobj = obj_on && obj_uses_kappa(a.obj.kind);
     const bool seeds = obj_on && (WB || !kobj);  // kappa objectives vanish off the footprint
-    const double sc = a.obj.scale;
+    const T scT = (T)a.obj.scale;
     const LKS_GLOBAL T *__restrict__ Pin = gld(a.Pin);
     const LKS_GLOBAL T *__restrict__ Vin0 = gld(a.Vin[0]);
     const LKS_GLOBAL T *__restrict__ Vin1 = gld(a.Vin[1]);
@@ -789,14 +789,14 @@ __device__ __forceinline__ void adj2d_march(const AdjArgs<T> &a, int strip, int 
         const bool mk = want_mask ? qm[s] != 0 : true;
         if (j + AH < NJ) issue(j + AH);
 
-        // lambda + dj/dX, then the force transpose
+        // lambda + dj/dX (in the path's precision), then the force transpose
         if (seeds && cval && mk && !(kobj && kap == T(0))) {
-            const double us[3] = {(double)usx, (double)usy, 0.0};
-            double dP, dV[3];
-            obj_dstate(a.obj, c, r, 0, (double)kap, us, dP, dV);
-            P += (T)(sc * dP);
-            Vx += (T)(sc * dV[0]);
-            Vy += (T)(sc * dV[1]);
+            const T us[3] = {usx, usy, T(0)};
+            T dP, dV[3];
+            obj_dstate_r<T>(a.obj, c, r, 0, kap, us, dP, dV);
+            P += scT * dP;
+            Vx += scT * dV[0];
+            Vy += scT * dV[1];
         }
         if (XF) {  // boundary transpose of the x face
             const T pL = from_left(P), xL = from_left(Vx), yL = from_left(Vy);
@@ -813,13 +813,12 @@ __device__ __forceinline__ void adj2d_march(const AdjArgs<T> &a, int strip, int 
         }
         // kappa_bar on the wave's own footprint nodes of its output rows
         if (WB && j >= 2 && j < RM + 2 && out_lane && inb) {
-            double kb = -((double)Vx * ((double)ucx - (double)usx) + (double)Vy * ((double)ucy - (double)usy));
+            T kb = -(Vx * (ucx - usx) + Vy * (ucy - usy));
             if (kobj && mk) {
-                const double uu[3] = {(double)ucx, (double)ucy, 0.0};
-                const double uss[3] = {(double)usx, (double)usy, 0.0};
-                kb += sc * obj_dkappa(a.obj, c, r, 0, uu, uss);
+                const T uu[3] = {ucx, ucy, T(0)}, uss[3] = {usx, usy, T(0)};
+                kb += scT * obj_dkappa_r<T>(a.obj, c, r, 0, uu, uss);
             }
-            gst(a.kbar)[box_index(a.box, a.m, 2, c, r, 0)] = (T)kb;
+            gst(a.kbar)[box_index(a.box, a.m, 2, c, r, 0)] = kb;
         }
 
         // x-stencils of row r: a0 = M0 P + M1 Vx, a1 = M1 P + M2 Vx, a2 = M2 P + M1 Vx, b_k = M_k Vy
@@ -912,7 +911,7 @@ __host__ __device__ inline Adj2dUnits adj2d_units(const Geom &g) {
     u.ngs = u.nstrips - u.ninner;
     u.nms = u.ninner + ((u.nmc > 0 && !g.per[0]) ? u.ngs : 0);  // marching strips
     u.ngr = (ny + RGA - 1) / RGA;
-    u.neg = u.nms > 0 ? 2 + (ny - u.yhi + RGA - 1) / RGA : 0;
+    u.neg = u.nms > 0 ? 4 + (ny - u.yhi) : 0;  // y-edge units of one row each
     u.nmarch = (long long)u.nms * u.nmc;
     u.nouter = u.nms > u.ninner ? 0 : (long long)u.ngs * u.ngr;
     u.total = u.nmarch + u.nouter + (long long)u.nms * u.neg;
@@ -952,7 +951,9 @@ __device__ __forceinline__ void adj2d_unit(const AdjArgs<T> &a, const Adj2dUnits
         const int v = (int)(k - u.nmarch - u.nouter);
         const int q = v / u.nms;
         strip = adj2d_mstrip(u, v % u.nms);
-        y0 = q < 2 ? RGA * q : u.yhi + RGA * (q - 2);
+        y0 = q < 4 ? q : u.yhi + (q - 4);
+        adj2d_rows<T, false, 1>(a, strip, y0);  // one row: these general units finish with the marches
+        return;
     }
     adj2d_rows<T, false, RGA>(a, strip, y0);
 }
