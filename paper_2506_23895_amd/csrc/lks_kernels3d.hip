@@ -802,6 +802,21 @@ __device__ __forceinline__ void adj3d_main_body(const AdjArgs<T> &a, int bx, int
     for (int t = 0; t < 3; ++t) ru[t][0] = ru[t][1] = ru[t][2] = ru[t][3] = T(0);
     const T A2 = T(2) * a.A;
 
+    // transposed x- and y-derivatives of s~ at this thread's output column: central where every
+    // column (row) of the block is at least three nodes from a face (or the axis is periodic),
+    // else through coefficients that depend on the column (row) only, formed once here
+    const int gxo = x0 + ox, gyo = y0 + oy;
+    const bool xcen = g.per[0] || (x0 >= 3 && x0 + TX <= nx - 3);  // block-uniform
+    const bool ycen = g.per[1] || (y0 >= 3 && y0 + TY <= ny - 3);
+    T dcx[5], dcy[5];
+#pragma unroll
+    for (int o = 0; o < 5; ++o) {
+        T f[5] = {T(0), T(0), T(0), T(0), T(0)};
+        f[o] = T(1);
+        dcx[o] = deriv_T3(f, gxo, nx, g.per[0]);
+        dcy[o] = deriv_T3(f, gyo, ny, g.per[1]);
+    }
+
     for (int zm = zfirst; zm <= ze - 1 + LAG; ++zm) {
         fetch_pv(zm + 2);  // in flight during the moment pass
         int zw = zm;
@@ -866,12 +881,22 @@ __device__ __forceinline__ void adj3d_main_body(const AdjArgs<T> &a, int bx, int
                 T f[5];
                 const int cx_ = sidx[aa][0], cy_ = sidx[aa][1], cz_ = sidx[aa][2];
                 const T *px = s_plane<T, PZ>(ss, cx_, zo), *py = s_plane<T, PZ>(ss, cy_, zo);
+                if (xcen) {
+                    v[aa] += A2 * (T(0.5) * (px[c0 - 1] - px[c0 + 1]));
+                } else {
+                    T d = T(0);
 #pragma unroll
-                for (int o = 0; o < 5; ++o) f[o] = px[c0 + o - 2];
-                v[aa] += A2 * deriv_T3(f, gx, nx, g.per[0]);
+                    for (int o = 0; o < 5; ++o) d += dcx[o] * px[c0 + o - 2];
+                    v[aa] += A2 * d;
+                }
+                if (ycen) {
+                    v[aa] += A2 * (T(0.5) * (py[c0 - MX] - py[c0 + MX]));
+                } else {
+                    T d = T(0);
 #pragma unroll
-                for (int o = 0; o < 5; ++o) f[o] = py[c0 + (o - 2) * MX];
-                v[aa] += A2 * deriv_T3(f, gy, ny, g.per[1]);
+                    for (int o = 0; o < 5; ++o) d += dcy[o] * py[c0 + (o - 2) * MX];
+                    v[aa] += A2 * d;
+                }
                 if (PZ) {  // periodic z: the central difference reads planes zo - 1 and zo + 1 only
                     f[0] = f[2] = f[4] = T(0);
                     f[1] = s_plane<T, PZ>(ss, cz_, zo - 1)[c0];
