@@ -82,11 +82,16 @@ def bytes_per_lup(cfg: dict) -> dict:
 
 
 def kernel_source_hash() -> str:
-    """Hash of the device-code sources (the host runtime lks_api.hip is not part of it)."""
+    """Hash of the device-code sources (the host runtime lks_api.hip is not part of it), with
+    comments and whitespace removed, so that documentation edits keep measured profiles valid."""
+    import re
     h = hashlib.sha256()
     for f in sorted(os.listdir(os.path.join(ROOT, "paper_2506_23895_amd", "csrc"))):
         if f.endswith((".hip", ".hpp")) and f != "lks_api.hip":
-            h.update(open(os.path.join(ROOT, "paper_2506_23895_amd", "csrc", f), "rb").read())
+            text = open(os.path.join(ROOT, "paper_2506_23895_amd", "csrc", f)).read()
+            text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+            text = re.sub(r"//[^\n]*", " ", text)
+            h.update(f.encode() + b"\0" + " ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -1,6 +1,10 @@
 // 2D D2Q9 kernels: one fused forward step and one fused adjoint step per launch, both on wave
 // strips: the 64 lanes of a wave hold 64 consecutive columns and the wave walks a few rows, so
 // x-neighbours are one lane away (DPP row shifts) and y-neighbours are registers of the same lane.
+// Each launch is a list of work units, one per wave, sized so that no kind of wave outlives the
+// rest: interior units (no face, no wrap) run compiled-out variants, units of a strip that holds
+// an x face run the XF variants (that one face's rule inline), and the rows next to the y faces
+// (or a periodic axis's wrap) run the general variants with the composite boundary rules.
 //
 // Forward step (Algorithm 1 body, Sec. 2.2-2.3): lanes 2..61 own output columns, the two lanes on
 // each side are the u halo.  Every row the wave needs (u with halo 2, rho - 1 with halo 1, kappa
