@@ -51,6 +51,12 @@ CASES = {
              _bc("NOSLIP"), _bc("NOSLIP", 1.0, (0.01, 0, 0))]),
     # walls on the y faces (one moving), a pressure outlet, periodic z: the y-face rules of every 3D
     # kernel and the one-sided transposed y-derivatives of the adjoint
+    # walls on the y and z faces: the composite rules of the edges and corners where two or three
+    # non-periodic faces meet (rotating body, drag)
+    "d3q19_yzwalls_drag": dict(
+        obj="DRAG", n=(36, 27, 25),
+        bcs=[_bc("VELOCITY", 1.0, (0.03, 0, 0)), _bc("ZERO_GRADIENT"),
+             _bc("NOSLIP"), _bc("NOSLIP", 1.0, (0.01, 0, 0)), _bc("NOSLIP"), _bc("NOSLIP", 1.0, (0, 0.01, 0))]),
     "d3q19_ywalls_drag": dict(
         obj="DRAG", n=(40, 27, 21),
         bcs=[_bc("VELOCITY", 1.0, (0.03, 0, 0)), _bc("PRESSURE", 1.001, (0, 0.002, 0.001)),
