@@ -57,6 +57,8 @@ CASES = {
         obj="DRAG", n=(36, 27, 25),
         bcs=[_bc("VELOCITY", 1.0, (0.03, 0, 0)), _bc("ZERO_GRADIENT"),
              _bc("NOSLIP"), _bc("NOSLIP", 1.0, (0.01, 0, 0)), _bc("NOSLIP"), _bc("NOSLIP", 1.0, (0, 0.01, 0))]),
+    # a footprint box that moves along y (heave with pitch) and the power objective
+    "d3q19_heave_power": dict(obj="POWER", motion="heave"),
     "d3q19_ywalls_drag": dict(
         obj="DRAG", n=(40, 27, 21),
         bcs=[_bc("VELOCITY", 1.0, (0.03, 0, 0)), _bc("PRESSURE", 1.001, (0, 0.002, 0.001)),
