@@ -72,6 +72,24 @@ def motion_rotation(nsteps: int, centre: Sequence[float], omega: float, theta0: 
     return out
 
 
+def motion_rotation_axis(nsteps: int, centre: Sequence[float], omega: float,
+                         axis: Sequence[float]) -> np.ndarray:
+    """Rotation about a fixed unit ``axis`` through ``centre`` at constant angular velocity:
+    R(t) from the axis-angle (Rodrigues) form, Omega = omega * axis."""
+    a = np.asarray(axis, dtype=np.float64)
+    a = a / np.linalg.norm(a)
+    K = np.array([[0.0, -a[2], a[1]], [a[2], 0.0, -a[0]], [-a[1], a[0], 0.0]])
+    out = np.zeros((nsteps + 1, MOTION_REC))
+    for n in range(nsteps + 1):
+        th = omega * n
+        R = np.eye(3) + math.sin(th) * K + (1.0 - math.cos(th)) * (K @ K)
+        out[n, 0:9] = R.reshape(-1)
+        out[n, 9:12] = omega * a
+        out[n, 12:15] = centre
+        out[n, 15:18] = 0.0
+    return out
+
+
 def motion_heave(nsteps: int, centre: Sequence[float], amp: float, omega: float,
                  theta_amp: float = 0.0) -> np.ndarray:
     """Vertical heave y_G = y_c + amp sin(omega t) with optional pitching theta = theta_amp sin(omega t)."""

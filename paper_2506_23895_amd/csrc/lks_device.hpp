@@ -105,6 +105,59 @@ __device__ __forceinline__ void gather_kappa(const Design<T> &des, const StepMot
 #pragma unroll
     for (int a = 0; a < dim; ++a) inv[a] = fabs(R[3 * a]) > T(1e-6) ? T(1) / R[3 * a] : T(0);
     T sW = 0, sWk = 0, sWd[3] = {0, 0, 0};
+    if (DIM == 3 && m.R[2] == 0.0 && m.R[5] == 0.0 && m.R[6] == 0.0 && m.R[7] == 0.0 &&
+        m.R[8] == 1.0) {
+        // Rotation about z (the same for the whole launch): d_z depends on the plane alone and
+        // the x/y window is the same on every plane, so the x/y weights are formed once per
+        // (i, j) and the planes of the support (at most 2s + 1 <= 5) are summed innermost.
+        constexpr int MK = 5;
+        const int nk = hi[2] - lo[2] + 1;
+        T wz[MK], dz[MK];
+#pragma unroll
+        for (int kk = 0; kk < MK; ++kk) {
+            dz[kk] = d0[2] - (T)kk;
+            wz[kk] = kk < nk ? wk<T>(des.weight, dz[kk]) : T(0);
+        }
+        const long long pst = (long long)des.nd[0] * des.nd[1];
+        const int kl = max(nk - 1, 0);
+        for (int j = lo[1]; j <= hi[1] && nk > 0; ++j) {
+            const T fj = (T)(j - lo[1]);
+            T flo = T(0), fhi = span;
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const T ca = d0[a] - fj * R[3 * a + 1];
+                if (inv[a] != T(0)) {
+                    const T t1 = (ca - sT) * inv[a], t2 = (ca + sT) * inv[a];
+                    flo = fmax(flo, fmin(t1, t2) - T(1e-3));
+                    fhi = fmin(fhi, fmax(t1, t2) + T(1e-3));
+                } else if (fabs(ca) >= sT + T(1e-3)) {
+                    fhi = T(-1);
+                }
+            }
+            if (flo > fhi) continue;
+            const int i0 = lo[0] + (int)ceil(flo), i1 = lo[0] + (int)floor(fhi);
+            const T *krow = des.kref + (long long)des.nd[0] * (j + (long long)des.nd[1] * lo[2]);
+            for (int i = i0; i <= i1; ++i) {
+                const T fi = (T)(i - lo[0]);
+                const T dx = d0[0] - fi * R[0] - fj * R[1], dy = d0[1] - fi * R[3] - fj * R[4];
+                const T wxy = wk<T>(des.weight, dx) * wk<T>(des.weight, dy);
+                if (wxy == T(0)) continue;
+                // planes beyond the support read the last one (a valid node) with weight zero
+                T kv[MK];
+#pragma unroll
+                for (int kk = 0; kk < MK; ++kk) kv[kk] = krow[i + min(kk, kl) * pst];
+#pragma unroll
+                for (int kk = 0; kk < MK; ++kk) {
+                    const T W = wxy * wz[kk];
+                    sW += W;
+                    sWk += W * kv[kk];
+                    sWd[0] += W * dx;
+                    sWd[1] += W * dy;
+                    sWd[2] += W * dz[kk];
+                }
+            }
+        }
+    } else
     for (int k = lo[2]; k <= hi[2]; ++k) {
         const T fk = (T)(k - lo[2]);
         for (int j = lo[1]; j <= hi[1]; ++j) {

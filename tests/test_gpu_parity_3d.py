@@ -23,6 +23,8 @@ def box3(n=(40, 19, 37), nd=(9, 8, 7), N=24, K=7, prec="F64", lattice="D3Q19", w
     centre = (centre[0] + 0.3, centre[1] - 0.2, centre[2] + 0.1)
     if motion == "rotate":
         mot = I.motion_rotation(N, centre, 2 * math.pi / 80)
+    elif motion == "tilt":
+        mot = I.motion_rotation_axis(N, centre, 2 * math.pi / 80, (0.36, 0.48, 0.8))
     else:
         mot = I.motion_heave(N, centre, 1.5, 2 * math.pi / 40, theta_amp=0.3)
     if bcs is None:
@@ -59,6 +61,9 @@ CASES = {
              _bc("NOSLIP"), _bc("NOSLIP", 1.0, (0.01, 0, 0)), _bc("NOSLIP"), _bc("NOSLIP", 1.0, (0, 0.01, 0))]),
     # a footprint box that moves along y (heave with pitch) and the power objective
     "d3q19_heave_power": dict(obj="POWER", motion="heave"),
+    # rotation about a tilted axis: the general transfer (no plane-separable weights), the
+    # paper's cosine kernel, torque about z
+    "d3q19_tilted_axis_cos4_torque": dict(motion="tilt", weight="COS4", interp="PAPER", kmax=2.0),
     "d3q19_ywalls_drag": dict(
         obj="DRAG", n=(40, 27, 21),
         bcs=[_bc("VELOCITY", 1.0, (0.03, 0, 0)), _bc("PRESSURE", 1.001, (0, 0.002, 0.001)),

@@ -36,6 +36,8 @@ def tiny_cfg(dim=2, lattice="D2Q9", weight="LIN", interp="FLUID_ONE", obj="DRAG"
         mot = I.motion_rotation(N, centre, 2 * math.pi / 60)
     elif motion == "heave":
         mot = I.motion_heave(N, centre, 0.7, 2 * math.pi / 40, theta_amp=0.3)
+    elif motion == "tilt":
+        mot = I.motion_rotation_axis(N, centre, 2 * math.pi / 60, (0.36, 0.48, 0.8))
     else:
         mot = I.motion_static(N, centre)
     if bcs is None:
@@ -85,6 +87,8 @@ FD_CASES = {
                             _bc("VELOCITY", 1.0, (0.02, 0, 0)), _bc("PERIODIC"), _bc("PERIODIC")]),
     "d3q19": dict(dim=3, lattice="D3Q19"),
     "d3q15_cos4_torque": dict(dim=3, lattice="D3Q15", weight="COS4", obj="TORQUE"),
+    "d3q19_tilted_axis_cos4": dict(dim=3, lattice="D3Q19", weight="COS4", obj="TORQUE",
+                                   motion="tilt", n=(12, 11, 11)),
     "d3q19_walls": dict(dim=3, lattice="D3Q19", obj="POWER",
                         bcs=[_bc("VELOCITY", 1.0, (0.03, 0, 0)), _bc("ZERO_GRADIENT"), _bc("NOSLIP"),
                              _bc("NOSLIP"), _bc("PRESSURE", 1.0), _bc("ZERO_GRADIENT")]),
@@ -471,6 +475,51 @@ def test_P8_rigid_map_isometry_and_velocity():
         kap, uS = O.transfer(cfg1, 2, np.ones(1))
         v = uS[:2].sum(axis=1) / kap.sum()
         assert np.abs(v - vel_fd[p]).max() < 5e-3 * max(1.0, np.abs(vel_fd[p]).max())
+
+
+def test_P8_rigid_map_isometry_and_velocity_3d_tilted_axis():
+    """The same recovery in 3D for a rotation about a tilted axis (trilinear hats): distances
+    between design points are preserved, points on the axis stay put, and u_S / sum(W) equals
+    dx_ref/dt (central FD in time)."""
+    n = (20, 20, 20)
+    N = 4
+    centre = (9.3, 10.1, 9.6)
+    axis = np.array([0.36, 0.48, 0.8])
+    mot = I.motion_rotation_axis(N, centre, 0.21, axis)
+    nd = (3, 3, 3)
+    xi_G = (1.0, 1.0, 1.0)
+    cfg = I.make_config(dim=3, lattice="D3Q19", n=n, nd=nd, nu=0.1, nsteps=N, motion=mot,
+                        bcs=I.periodic_bcs(), obj=I.objective("NONE", 1, 0), weight="LIN", xi_G=xi_G)
+    idx = np.arange(n[0] * n[1] * n[2])
+    X = np.stack([idx % n[0], (idx // n[0]) % n[1], idx // (n[0] * n[1])], axis=1).astype(float)
+
+    def points(step, c=cfg, npts=27):
+        P = []
+        for p in range(npts):
+            kr = np.zeros(npts)
+            kr[p] = 1.0
+            kap, _ = O.transfer(c, step, kr)
+            P.append(kap @ X / kap.sum())
+        return np.array(P)
+
+    P2 = points(2)
+    xi = np.array([(i, j, k) for k in range(3) for j in range(3) for i in range(3)], dtype=float)
+    dP = np.linalg.norm(P2[:, None] - P2[None], axis=-1)
+    dX = np.linalg.norm(xi[:, None] - xi[None], axis=-1)
+    assert np.abs(dP - dX).max() < 1e-12
+    assert np.abs(P2[13] - np.asarray(centre)).max() < 1e-12        # xi_G sits on the axis
+    vel_fd = (points(3) - points(1)) / 2.0
+    assert np.abs(vel_fd[13]).max() < 1e-12
+    for p in (0, 5, 22):
+        i, j, k = p % 3, (p // 3) % 3, p // 9
+        c1 = I.make_config(dim=3, lattice="D3Q19", n=n, nd=(1, 1, 1), nu=0.1, nsteps=N, motion=mot,
+                           bcs=I.periodic_bcs(), obj=I.objective("NONE", 1, 0), weight="LIN",
+                           xi_G=(xi_G[0] - i, xi_G[1] - j, xi_G[2] - k))
+        kap, uS = O.transfer(c1, 2, np.ones(1))
+        v = uS[:3].sum(axis=1) / kap.sum()
+        assert np.abs(v - vel_fd[p]).max() < 5e-3 * max(1.0, np.abs(vel_fd[p]).max())
+        # rigid velocity is perpendicular to the axis
+        assert abs(np.dot(v, axis)) < 1e-12
 
 
 def test_interp_forms():
