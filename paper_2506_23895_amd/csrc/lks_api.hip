@@ -127,6 +127,7 @@ int plan(const lks_desc *d, Layout &L, std::string *err) {
     L.ncell = (long long)g.n[0] * g.n[1] * g.n[2];
     L.nd = (long long)d->nd[0] * d->nd[1] * d->nd[2];
     L.esz = d->precision == LKS_F64 ? 8 : 4;
+    g.zc = D == 3 ? lks::choose_zc3(g, (int)L.esz) : 1;
     const int N = d->nsteps;
     L.fwd_only = d->objective.kind == LKS_OBJ_NONE;  // nothing to differentiate: no reverse buffers
     L.K = (L.fwd_only || d->checkpoint_every == 0 || d->checkpoint_every >= N) ? N : d->checkpoint_every;

@@ -14,6 +14,7 @@ struct Geom {
     int n[3];
     int per[3];        // 1 if the axis is periodic (always 1 for axes >= dim)
     long long sy, sz;  // element strides
+    int zc;            // 3D: z planes marched per block (chosen at create from the grid size)
 };
 
 // Boundary kinds per face (x-, x+, y-, y+, z-, z+); rho is stored as rho - 1.
@@ -183,5 +184,6 @@ long long xfer_blocks3d(long long cells, int esz);
 // grid sizes of the stencil launches (used by the host to size the partials buffer)
 long long fwd_blocks(const Geom &g, int lattice, int esz);
 long long fwd_blocks3d(const Geom &g, int lattice, int esz);
+int choose_zc3(const Geom &g, int esz);  // z planes per block of the 3D marching kernels
 
 }  // namespace lks

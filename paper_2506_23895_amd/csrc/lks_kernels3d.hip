@@ -1,11 +1,12 @@
 // 3D kernels (D3Q19 and D3Q15).
 //
 // Forward step, marching along z (Algorithm 1 body, Sec. 2.2-2.3): a block owns a TX x TY column
-// of output nodes and a chunk of ZC planes.  Velocity planes z-2 .. z+2 (x-y halo 2) sit in an
-// LDS ring; the equilibrium E_i of plane z (x-y halo 1) is evaluated once into LDS; each thread
-// then adds the E_i pulled by its own column into three in-flight output planes held in
-// registers (c_z = -1 completes plane z-1, c_z = 0 feeds plane z, c_z = +1 plane z+1), and
-// finishes plane z-1: transfer gather, VPM update, composite boundary rules, objective partial.
+// of output nodes and a chunk of zc planes (chosen per grid, 8..32, by choose_zc3).  Velocity
+// planes z-2 .. z+2 (x-y halo 2) sit in an LDS ring; the equilibrium E_i of plane z (x-y halo 1)
+// is evaluated once into LDS; each thread then adds the E_i pulled by its own column into three
+// in-flight output planes held in registers (c_z = -1 completes plane z-1, c_z = 0 feeds plane z,
+// c_z = +1 plane z+1), and finishes plane z-1: transfer gather, VPM update, composite boundary
+// rules, objective partial.
 // The next velocity plane is fetched into registers before the stencil work of the current one.
 //
 // Adjoint step in two kernels.  The first is pointwise: lambda = Lambda^n + dj^n/dX^n, the
@@ -50,7 +51,7 @@ struct Tile3 {};
 #endif
 template <>
 struct Tile3<float> {
-    static constexpr int TX = 32, TY = 8, ZC = LKS_FWD3D_ZC;  // z planes marched per block
+    static constexpr int TX = 32, TY = 8, ZC = LKS_FWD3D_ZC;  // longest z chunk of a block
 };
 template <>
 struct Tile3<double> {
@@ -121,7 +122,7 @@ __device__ __forceinline__ int uring(int z) { return PZ ? ring3(z) : ring5(z); }
 
 template <typename T, int Q, bool PZ>
 __device__ __forceinline__ void fwd3d_body(const FwdArgs<T> &a, int bx, int by, int bz, long long blin, T *lds) {
-    constexpr int TX = Tile3<T>::TX, TY = Tile3<T>::TY, ZC = Tile3<T>::ZC, NT = TX * TY;
+    constexpr int TX = Tile3<T>::TX, TY = Tile3<T>::TY, NT = TX * TY;
     constexpr int UX = TX + 4, UY = TY + 4, UP = UX * UY;  // velocity plane, halo 2
     constexpr int EX = TX + 2, EY = TY + 2, EP = EX * EY;  // E_i plane, halo 1
     constexpr int NU = (UP + NT - 1) / NT, NE = (EP + NT - 1) / NT;
@@ -134,8 +135,8 @@ __device__ __forceinline__ void fwd3d_body(const FwdArgs<T> &a, int bx, int by, 
     const Geom &g = a.g;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     const int tid = threadIdx.x;
-    const int x0 = bx * TX, y0 = by * TY, zs = bz * ZC;
-    const int ze = min(zs + ZC, nz);
+    const int x0 = bx * TX, y0 = by * TY, zs = bz * g.zc;
+    const int ze = min(zs + g.zc, nz);
     const T A = a.A;
     // block-uniform: E or output nodes of the block on or next to a non-periodic x / y face
     const bool xface = !g.per[0] && (x0 - 1 <= 1 || x0 + TX >= nx - 2);
@@ -450,7 +451,7 @@ __device__ __forceinline__ void tile_coords3(const Geom &g, long long t, int &bx
     const int nbx = (g.n[0] + Tile3<T>::TX - 1) / Tile3<T>::TX;
     const int nby = (g.n[1] + Tile3<T>::TY - 1) / Tile3<T>::TY;
 #if LKS_XCD3D
-    const unsigned tu = (unsigned)xcd_tile(t, (long long)nbx * nby * ((g.n[2] + Tile3<T>::ZC - 1) / Tile3<T>::ZC));
+    const unsigned tu = (unsigned)xcd_tile(t, (long long)nbx * nby * ((g.n[2] + g.zc - 1) / g.zc));
 #else
     const unsigned tu = (unsigned)t;
 #endif
@@ -462,7 +463,7 @@ __device__ __forceinline__ void tile_coords3(const Geom &g, long long t, int &bx
 template <typename T>
 __device__ __forceinline__ long long stencil_tiles3(const Geom &g) {
     return (long long)((g.n[0] + Tile3<T>::TX - 1) / Tile3<T>::TX) *
-           ((g.n[1] + Tile3<T>::TY - 1) / Tile3<T>::TY) * ((g.n[2] + Tile3<T>::ZC - 1) / Tile3<T>::ZC);
+           ((g.n[1] + Tile3<T>::TY - 1) / Tile3<T>::TY) * ((g.n[2] + g.zc - 1) / g.zc);
 }
 
 // PZ: every job of the launch is periodic in z (the three-plane velocity ring; dynamic LDS sized
@@ -718,7 +719,7 @@ __device__ __forceinline__ T *s_plane(T *ss, int c, int z) {
 template <typename T, int Q, bool PZ>
 __device__ __forceinline__ void adj3d_main_body(const AdjArgs<T> &a, int bx, int by, int bz, T *lds) {
     using L = Adj3Lds<T>;
-    constexpr int TX = L::TX, TY = L::TY, ZC = Tile3<T>::ZC, NT = TX * TY;
+    constexpr int TX = L::TX, TY = L::TY, NT = TX * TY;
     constexpr int PX = L::PX, PP = L::PP, MX = L::MX, MP = L::MP;
     constexpr int NP = (PP + NT - 1) / NT;
     constexpr int NH = MP - NT;  // halo moment nodes
@@ -730,8 +731,8 @@ __device__ __forceinline__ void adj3d_main_body(const AdjArgs<T> &a, int bx, int
     const Geom &g = a.g;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     const int tid = threadIdx.x;
-    const int x0 = bx * TX, y0 = by * TY, zs = bz * ZC;
-    const int ze = min(zs + ZC, nz);
+    const int x0 = bx * TX, y0 = by * TY, zs = bz * g.zc;
+    const int ze = min(zs + g.zc, nz);
     const int ox = tid % TX, oy = tid / TX;
 
     T preg[NP][4];
@@ -940,8 +941,25 @@ long long fwd_blocks3d(const Geom &g, int lattice, int esz) {
     (void)lattice;
     const int TX = esz == 8 ? Tile3<double>::TX : Tile3<float>::TX;
     const int TY = esz == 8 ? Tile3<double>::TY : Tile3<float>::TY;
-    const int ZC = esz == 8 ? Tile3<double>::ZC : Tile3<float>::ZC;
-    return (long long)((g.n[0] + TX - 1) / TX) * ((g.n[1] + TY - 1) / TY) * ((g.n[2] + ZC - 1) / ZC);
+    return (long long)((g.n[0] + TX - 1) / TX) * ((g.n[1] + TY - 1) / TY) * ((g.n[2] + g.zc - 1) / g.zc);
+}
+
+// z planes marched per block: the longest chunk (Tile3::ZC) while the grid still yields about
+// one block per slot of the chip (256 CUs x 4); halved, down to 8 planes, for smaller grids, where
+// a launch would otherwise last as long as one block's march (a block also loads and evaluates
+// 2-4 planes beyond its chunk, which is why the floor is not lower); then evened out over the
+// chunks of nz.  Measured on the served mix (3D jobs 64^3..160^3 get 8 planes): 3.0 -> 3.35
+// evals/s batched, 2.4 -> 3.25 one job at a time; 256^3 keeps 32 (16 was slower there).
+int choose_zc3(const Geom &g, int esz) {
+    constexpr long long kTargetBlocks = 1024;
+    constexpr int kMinPlanes = 8;
+    const int TX = esz == 8 ? Tile3<double>::TX : Tile3<float>::TX;
+    const int TY = esz == 8 ? Tile3<double>::TY : Tile3<float>::TY;
+    const long long cols = (long long)((g.n[0] + TX - 1) / TX) * ((g.n[1] + TY - 1) / TY);
+    int zc = esz == 8 ? Tile3<double>::ZC : Tile3<float>::ZC;
+    while (zc > kMinPlanes && cols * ((g.n[2] + zc - 1) / zc) < kTargetBlocks) zc /= 2;
+    const int nch = (g.n[2] + zc - 1) / zc;
+    return (g.n[2] + nch - 1) / nch;
 }
 
 long long tiles3d(const Geom &g, int esz) { return fwd_blocks3d(g, 0, esz); }
