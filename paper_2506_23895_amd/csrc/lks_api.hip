@@ -128,6 +128,7 @@ int plan(const lks_desc *d, Layout &L, std::string *err) {
     L.nd = (long long)d->nd[0] * d->nd[1] * d->nd[2];
     L.esz = d->precision == LKS_F64 ? 8 : 4;
     g.zc = D == 3 ? lks::choose_zc3(g, (int)L.esz) : 1;
+    g.zca = D == 3 ? lks::choose_zca3(g, (int)L.esz) : 1;
     const int N = d->nsteps;
     L.fwd_only = d->objective.kind == LKS_OBJ_NONE;  // nothing to differentiate: no reverse buffers
     L.K = (L.fwd_only || d->checkpoint_every == 0 || d->checkpoint_every >= N) ? N : d->checkpoint_every;
@@ -545,7 +546,7 @@ int launch_adj_dev(lks_ctx *c, const lks::AdjArgs<T> *dargs, const lks::SensArgs
         e = c->d.dim == 2
                 ? lks::launch_adj2d_batch<T>(dargs, c->tile0, 1, lks::tiles2d(c->L.g), c->stream)
                 : lks::launch_adj3d_batch<T>(dargs, c->tile0, (c->L.ncell + lks::kBlockHost - 1) / lks::kBlockHost,
-                                             c->tile0, lks::tiles3d(c->L.g, (int)c->L.esz), 1,
+                                             c->tile0, lks::tiles3d_adj(c->L.g, (int)c->L.esz), 1,
                                              c->d.lattice, c->L.g.per[2] != 0, c->stream);
     }
     HIPCHK(c, e);
@@ -1004,7 +1005,7 @@ int list_of(const lks_ctx *c) { return c->d.dim == 2 ? 0 : (c->d.lattice == LKS_
 
 long long adj_tiles(const lks_ctx *c) {
     if (c->d.dim == 2) return lks::tiles2d(c->L.g);
-    return lks::tiles3d(c->L.g, (int)c->L.esz);
+    return lks::tiles3d_adj(c->L.g, (int)c->L.esz);
 }
 
 template <typename T>

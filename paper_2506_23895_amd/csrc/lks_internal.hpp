@@ -14,7 +14,8 @@ struct Geom {
     int n[3];
     int per[3];        // 1 if the axis is periodic (always 1 for axes >= dim)
     long long sy, sz;  // element strides
-    int zc;            // 3D: z planes marched per block (chosen at create from the grid size)
+    int zc;            // 3D: z planes marched per block of the forward (chosen at create)
+    int zca;           // 3D: z planes marched per block of the z-marching adjoint
 };
 
 // Boundary kinds per face (x-, x+, y-, y+, z-, z+); rho is stored as rho - 1.
@@ -184,6 +185,8 @@ long long xfer_blocks3d(long long cells, int esz);
 // grid sizes of the stencil launches (used by the host to size the partials buffer)
 long long fwd_blocks(const Geom &g, int lattice, int esz);
 long long fwd_blocks3d(const Geom &g, int lattice, int esz);
-int choose_zc3(const Geom &g, int esz);  // z planes per block of the 3D marching kernels
+int choose_zc3(const Geom &g, int esz);   // z planes per block of the 3D forward
+int choose_zca3(const Geom &g, int esz);  // ... of the z-marching adjoint (after zc is set)
+long long tiles3d_adj(const Geom &g, int esz);
 
 }  // namespace lks

@@ -447,11 +447,11 @@ __device__ __forceinline__ int job_of3(const long long *tile0, int njobs, long l
 // column (bx, by) and z chunk bz of the t-th dispatched block: each XCD takes a contiguous run of
 // tiles (x fastest), so blocks that share x-y halo planes read them through one L2
 template <typename T>
-__device__ __forceinline__ void tile_coords3(const Geom &g, long long t, int &bx, int &by, int &bz) {
+__device__ __forceinline__ void tile_coords3(const Geom &g, int zc, long long t, int &bx, int &by, int &bz) {
     const int nbx = (g.n[0] + Tile3<T>::TX - 1) / Tile3<T>::TX;
     const int nby = (g.n[1] + Tile3<T>::TY - 1) / Tile3<T>::TY;
 #if LKS_XCD3D
-    const unsigned tu = (unsigned)xcd_tile(t, (long long)nbx * nby * ((g.n[2] + g.zc - 1) / g.zc));
+    const unsigned tu = (unsigned)xcd_tile(t, (long long)nbx * nby * ((g.n[2] + zc - 1) / zc));
 #else
     const unsigned tu = (unsigned)t;
 #endif
@@ -483,7 +483,7 @@ __global__ __launch_bounds__(Tile3<T>::TX * Tile3<T>::TY) void k_fwd3d_batch(con
         return;
     }
     int bx, by, bz;
-    tile_coords3<T>(a.g, t, bx, by, bz);
+    tile_coords3<T>(a.g, a.g.zc, t, bx, by, bz);
     fwd3d_body<T, Q, PZ>(a, bx, by, bz, t, reinterpret_cast<T *>(fwd3_lds));
 }
 
@@ -731,8 +731,8 @@ __device__ __forceinline__ void adj3d_main_body(const AdjArgs<T> &a, int bx, int
     const Geom &g = a.g;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     const int tid = threadIdx.x;
-    const int x0 = bx * TX, y0 = by * TY, zs = bz * g.zc;
-    const int ze = min(zs + g.zc, nz);
+    const int x0 = bx * TX, y0 = by * TY, zs = bz * g.zca;
+    const int ze = min(zs + g.zca, nz);
     const int ox = tid % TX, oy = tid / TX;
 
     T preg[NP][4];
@@ -933,7 +933,7 @@ __global__ __launch_bounds__(Tile3<T>::TX * Tile3<T>::TY) void k_adj3d_main_batc
     const int j = __builtin_amdgcn_readfirstlane(job_of3(tile0, njobs, b));
     const AdjArgs<T> &a = args[j];
     int bx, by, bz;
-    tile_coords3<T>(a.g, njobs == 1 ? b : b - tile0[j], bx, by, bz);
+    tile_coords3<T>(a.g, a.g.zca, njobs == 1 ? b : b - tile0[j], bx, by, bz);
     adj3d_main_body<T, Q, PZ>(a, bx, by, bz, reinterpret_cast<T *>(adj3_lds));
 }
 
@@ -963,6 +963,37 @@ int choose_zc3(const Geom &g, int esz) {
 }
 
 long long tiles3d(const Geom &g, int esz) { return fwd_blocks3d(g, 0, esz); }
+
+long long tiles3d_adj(const Geom &g, int esz) {
+    const int TX = esz == 8 ? Tile3<double>::TX : Tile3<float>::TX;
+    const int TY = esz == 8 ? Tile3<double>::TY : Tile3<float>::TY;
+    return (long long)((g.n[0] + TX - 1) / TX) * ((g.n[1] + TY - 1) / TY) * ((g.n[2] + g.zca - 1) / g.zca);
+}
+
+// z planes per block of the z-marching adjoint.  Its LDS admits three FP32 blocks per CU (768
+// slots).  Where the forward keeps its longest chunk (a large grid), the adjoint takes the number
+// of chunks (at most the forward's) that minimises rounds x (planes + 3): the blocks of a round
+// run together, and a block marches about 3 planes beyond its chunk.  On 256^3 this picks 86
+// planes (one round), and the measured launch times follow the model's order: 86 planes 469 us,
+// 43 planes 477, 29 planes 489, 32 planes 506.  Elsewhere, and in FP64, the forward's chunk.
+int choose_zca3(const Geom &g, int esz) {
+    constexpr long long kAdjSlots = 768;
+    if (esz != 4 || g.zc < Tile3<float>::ZC) return g.zc;
+    const long long cols = (long long)((g.n[0] + Tile3<float>::TX - 1) / Tile3<float>::TX) *
+                           ((g.n[1] + Tile3<float>::TY - 1) / Tile3<float>::TY);
+    const int nz = g.n[2], nchf = (nz + g.zc - 1) / g.zc;
+    int best = nchf;
+    long long bestc = -1;
+    for (int nch = 1; nch <= nchf; ++nch) {
+        const long long rounds = (cols * nch + kAdjSlots - 1) / kAdjSlots;
+        const long long cost = rounds * ((nz + nch - 1) / nch + 3);
+        if (bestc < 0 || cost < bestc) {
+            bestc = cost;
+            best = nch;
+        }
+    }
+    return (nz + best - 1) / best;
+}
 
 long long xfer_blocks3d(long long cells, int esz) {
     const long long nt = esz == 8 ? Tile3<double>::TX * Tile3<double>::TY : Tile3<float>::TX * Tile3<float>::TY;
