@@ -505,10 +505,30 @@ int launch_fwd_dev(lks_ctx *c, const lks::FwdArgs<T> *dargs, int mode, hipStream
     return LKS_OK;
 }
 
-// transfer-only launch (not part of the per-step timing)
+// transfer-only launch (not part of the per-step timing); in 3D a kernel without LDS
 template <typename T>
 int launch_xfer_dev(lks_ctx *c, const lks::FwdArgs<T> *dargs, hipStream_t s) {
-    HIPCHK(c, (launch_fwd_raw<T>(c, dargs, fwd_tiles(c, lks::FWD_TRANSFER_NEXT), s)));
+    if (c->d.dim == 3)
+        HIPCHK(c, (lks::launch_xfer3d_batch<T>(dargs, c->tile0, 1, fwd_tiles(c, lks::FWD_TRANSFER_NEXT), s)));
+    else
+        HIPCHK(c, (launch_fwd_raw<T>(c, dargs, fwd_tiles(c, lks::FWD_TRANSFER_NEXT), s)));
+    return LKS_OK;
+}
+
+// one recomputed 3D step of the reverse sweep: the stencil tiles (with their LDS), then the
+// transfer of the next step as a launch of its own without LDS.  Fused, the transfer's many
+// short blocks each held the stencil's LDS and kept the adjoint launches of the other stream
+// waiting for it.
+template <typename T>
+int launch_fwd_split3(lks_ctx *c, const lks::FwdArgs<T> *dargs, int mode, hipStream_t s) {
+    hipError_t e;
+    {
+        Timed t(c, 0, s);
+        e = launch_fwd_raw<T>(c, dargs, fwd_tiles(c, mode & lks::FWD_STENCIL), s);
+        if (e == hipSuccess && (mode & lks::FWD_TRANSFER_NEXT))
+            e = lks::launch_xfer3d_batch<T>(dargs, c->tile0, 1, fwd_tiles(c, lks::FWD_TRANSFER_NEXT), s);
+    }
+    HIPCHK(c, e);
     return LKS_OK;
 }
 
@@ -834,7 +854,9 @@ int adjoint_impl(lks_ctx *c) {
             if ((rc = copy_fields<T>(c, t0[0], ck + L.F, D, sr))) return rc;
             if ((rc = launch_xfer_dev<T>(c, dra + nrec + ps, sr))) return rc;
             for (int n = p0; n <= p1; ++n)
-                if ((rc = launch_fwd_dev<T>(c, dra + (n - 1), ra[n - 1].mode, sr))) return rc;
+                if ((rc = D == 3 ? launch_fwd_split3<T>(c, dra + (n - 1), ra[n - 1].mode, sr)
+                                 : launch_fwd_dev<T>(c, dra + (n - 1), ra[n - 1].mode, sr)))
+                    return rc;
             if (sr != c->stream) HIPCHK(c, hipEventRecord(c->ev_rec, sr));
         }
         c->overlap = seg >= 1 && sr != c->stream;

@@ -168,6 +168,9 @@ template <typename T>
 hipError_t launch_fwd3d_batch(const FwdArgs<T> *args, const long long *tile0, int njobs,
                               long long ntiles, int lattice, bool pz, hipStream_t s);
 template <typename T>
+hipError_t launch_xfer3d_batch(const FwdArgs<T> *args, const long long *tile0, int njobs, long long ntiles,
+                               hipStream_t s);
+template <typename T>
 // pz: every job of the launch is periodic in z (smaller LDS layout of the z-marching kernel)
 hipError_t launch_adj3d_batch(const AdjArgs<T> *args, const long long *blk0, long long nblk,
                               const long long *tile0, long long ntiles, int njobs, int lattice, bool pz,

@@ -1014,6 +1014,29 @@ hipError_t launch_fwd3d_batch(const FwdArgs<T> *args, const long long *tile0, in
     return hipGetLastError();
 }
 
+// Transfer blocks alone, without the stencil's LDS: used where the transfer of the next step
+// runs beside launches of another stream (segment recompute during the reverse sweep) or with
+// no stencil at all, so that its many short blocks hold no LDS.
+template <typename T>
+__global__ __launch_bounds__(Tile3<T>::TX * Tile3<T>::TY) void k_xfer3d_batch(const FwdArgs<T> *__restrict__ args,
+                                                                            const long long *__restrict__ tile0,
+                                                                            int njobs) {
+    const long long b = blockIdx.x;
+    const int j = __builtin_amdgcn_readfirstlane(job_of3(tile0, njobs, b));
+    const FwdArgs<T> &a = args[j];
+    const long long t = njobs == 1 ? b : b - tile0[j];
+    transfer_box<T, 3, Tile3<T>::TX * Tile3<T>::TY>(a.des, a.mnext, a.box, a.knext, a.usnext, t);
+}
+
+template <typename T>
+hipError_t launch_xfer3d_batch(const FwdArgs<T> *args, const long long *tile0, int njobs, long long ntiles,
+                               hipStream_t s) {
+    if (njobs == 0 || ntiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_xfer3d_batch<T>, dim3((unsigned)ntiles), dim3(Tile3<T>::TX * Tile3<T>::TY), 0, s,
+                       args, tile0, njobs);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_adj3d_batch(const AdjArgs<T> *args, const long long *blk0, long long nblk,
                               const long long *tile0, long long ntiles, int njobs, int lattice, bool pz,
@@ -1034,7 +1057,9 @@ hipError_t launch_adj3d_batch(const AdjArgs<T> *args, const long long *blk0, lon
     template hipError_t launch_fwd3d_batch<T>(const FwdArgs<T> *, const long long *, int, long long,  \
                                               int, bool, hipStream_t);                                \
     template hipError_t launch_adj3d_batch<T>(const AdjArgs<T> *, const long long *, long long,       \
-                                              const long long *, long long, int, int, bool, hipStream_t);
+                                              const long long *, long long, int, int, bool, hipStream_t); \
+    template hipError_t launch_xfer3d_batch<T>(const FwdArgs<T> *, const long long *, int, long long,   \
+                                               hipStream_t);
 LKS_INST3(float)
 LKS_INST3(double)
 #undef LKS_INST3
