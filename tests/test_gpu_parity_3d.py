@@ -103,6 +103,25 @@ def test_c4_copy48_fp32():
     print(compare(cfg, g, **F32))
 
 
+@pytest.mark.parametrize("nz", [64, 128])
+def test_c4_slab_chunks_fp32(nz):
+    """C4's lattice parameters on a 256 x 256 x nz slab for 3 steps with a checkpoint every 2 (so
+    a segment is recomputed).  The z chunk is chosen per grid: nz = 64 marches 16-plane chunks in
+    the forward and the adjoint, nz = 128 marches 32-plane forward chunks and 43-plane adjoint
+    chunks (the adjoint's own choice on a large grid)."""
+    n, nd, N = (256, 256, nz), (96, 96, 40 if nz == 64 else 96), 3
+    centre = tuple((v - 1) / 2.0 for v in n)
+    bcs = [_bc("VELOCITY", 1.0, (0.02, 0, 0)), _bc("ZERO_GRADIENT"), _bc("PERIODIC"), _bc("PERIODIC"),
+           _bc("PERIODIC"), _bc("PERIODIC")]
+    cfg = I.make_config(dim=3, lattice="D3Q19", n=n, nd=nd, nu=0.0192, nsteps=N,
+                        motion=I.motion_rotation(N, centre, 2 * math.pi / 1500), bcs=bcs,
+                        obj=I.objective("TORQUE", 1, N, centre=centre, direction=(0, 0, 1)),
+                        u0=(0.02, 0, 0), precision="F32", checkpoint_every=2)
+    announce(f"c4 slab 256x256x{nz} fp32")
+    g = I.gamma_field(cfg["nd"], 3, 3)
+    print(compare(cfg, g, **F32))
+
+
 def test_c4_full_grid_short_fp32():
     """The benchmark's 3D launch configuration (256^3 grid, 96^3 design) on 3 steps."""
     cfg = I.config_c4(precision="F32", nsteps=3, checkpoint_every=2)
