@@ -441,6 +441,7 @@ lks::FwdArgs<T> base_fwd_args(lks_ctx *c) {
 template <typename T>
 void set_next(lks_ctx *c, lks::FwdArgs<T> &a, int n, T *knext) {
     a.mode |= lks::FWD_TRANSFER_NEXT;
+    if (c->d.weight == LKS_W_COS4) a.mode |= lks::FWD_TRANSFER_FIRST;
     a.mnext = c->L.steps[n];
     a.knext = knext;
     for (int k = 0; k < 3; ++k) a.usnext[k] = k < c->d.dim ? knext + (1 + k) * c->L.box.cells : nullptr;

@@ -82,7 +82,8 @@ struct FwdArgs {
     T *usnext[3];
     ObjParams obj;
 };
-enum { FWD_STENCIL = 1, FWD_TRANSFER_NEXT = 2 };
+// FWD_TRANSFER_FIRST (2D): the transfer blocks precede the stencil tiles in the launch
+enum { FWD_STENCIL = 1, FWD_TRANSFER_NEXT = 2, FWD_TRANSFER_FIRST = 4 };
 
 template <typename T>
 struct SensArgs;
