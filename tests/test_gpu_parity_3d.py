@@ -61,6 +61,10 @@ CASES = {
              _bc("NOSLIP"), _bc("NOSLIP", 1.0, (0.01, 0, 0)), _bc("NOSLIP"), _bc("NOSLIP", 1.0, (0, 0.01, 0))]),
     # a footprint box that moves along y (heave with pitch) and the power objective
     "d3q19_heave_power": dict(obj="POWER", motion="heave"),
+    # thin periodic z axes: the chunk is the whole column (fewer planes than the velocity ring
+    # reaches, so ring planes wrap onto the same data) and the footprint spans every plane
+    "d3q19_thin_periodic_z3": dict(n=(40, 19, 3), nd=(9, 8, 1)),
+    "d3q15_thin_periodic_z5": dict(lattice="D3Q15", n=(40, 19, 5), nd=(9, 8, 2)),
     # rotation about a tilted axis: the general transfer (no plane-separable weights), the
     # paper's cosine kernel, torque about z
     "d3q19_tilted_axis_cos4_torque": dict(motion="tilt", weight="COS4", interp="PAPER", kmax=2.0),
