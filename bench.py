@@ -138,7 +138,7 @@ def cpu_baseline(wl: str, cfg: dict, gamma: np.ndarray) -> dict:
                       f"{'forward + reverse' if grad else 'forward'}, FP64 C oracle, {dt:.1f} s"}
 
 
-def served_leg(n_req: int, rate: float, seed: int = 5) -> dict:
+def served_leg(n_req: int, rate: float, seed: int = 5, fill_cells: float = 0.0) -> dict:
     """Continuous batching vs back-to-back plain solves on one seeded Poisson request list."""
     from paper_2506_23895_amd.server import Request, Server, serve_plain, summarize
     rng = np.random.default_rng(seed)
@@ -147,7 +147,7 @@ def served_leg(n_req: int, rate: float, seed: int = 5) -> dict:
         t += float(rng.exponential(1.0 / rate))
         cfg = I.served_job(rng)
         reqs.append(Request(k, t, cfg, I.gamma_field(cfg["nd"], cfg["dim"], 100 + k)))
-    srv = Server()
+    srv = Server(fill_cells=fill_cells)
     served = summarize(srv.serve(reqs))
     rounds = srv.rounds
     srv.close()
@@ -296,6 +296,8 @@ def main() -> int:
     ap.add_argument("--requests", type=int, default=12, help="served leg: number of requests")
     ap.add_argument("--rate", type=float, default=50.0, help="served leg: arrivals per second")
     ap.add_argument("--no-served", action="store_true", help="skip the served leg")
+    ap.add_argument("--fill-cells", type=float, default=0.0,
+                    help="served leg: cells per round, shortest remaining work first (0: every job)")
     ap.add_argument("--nsteps", type=int, default=0, help="override the time horizon (profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--timing-every", type=int, default=8)
@@ -337,7 +339,7 @@ def main() -> int:
 
     if args.workload == "c5":
         t0 = time.perf_counter()
-        sv = served_leg(args.requests, args.rate)
+        sv = served_leg(args.requests, args.rate, fill_cells=args.fill_cells)
         dt = time.perf_counter() - t0
         print(json.dumps({
             "metric": "sens-evals/s served (continuous batching) + p50/p99 latency",
@@ -444,7 +446,7 @@ def main() -> int:
     solver.close()
     if has_adj and not args.no_served:
         print(f"[bench] served leg: {args.requests} requests at {args.rate}/s", flush=True)
-        line["served"] = served_leg(args.requests, args.rate)
+        line["served"] = served_leg(args.requests, args.rate, fill_cells=args.fill_cells)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, cfg, gamma)
     print(json.dumps(line), flush=True)

@@ -65,13 +65,29 @@ class _Active:
     nbytes: int
     admitted: float
     done: bool = False
+    rounds: int = 0         # micro-steps taken (a job needs about 2 N: forward, then reverse)
+
+    @property
+    def cells(self) -> int:
+        n = self.req.cfg["n"]
+        return int(n[0] * n[1] * n[2])
+
+    @property
+    def remaining(self) -> float:
+        return self.cells * max(1, 2 * self.req.cfg["nsteps"] - self.rounds)
 
 
 class Server:
-    def __init__(self, hbm_budget: int = 0, max_active: int = 32):
+    """fill_cells > 0: each round advances only the admitted jobs with the least remaining work
+    (cells x micro-steps left), as many as it takes to reach fill_cells cells in the round, so
+    that short jobs finish first instead of sharing every round with long ones; 0 advances every
+    admitted job every round."""
+
+    def __init__(self, hbm_budget: int = 0, max_active: int = 32, fill_cells: float = 0.0):
         free, total = torch.cuda.mem_get_info()
         self.budget = int(hbm_budget) if hbm_budget else int(0.8 * free)
         self.max_active = max_active
+        self.fill_cells = float(fill_cells)
         self.stream = torch.cuda.current_stream().cuda_stream
         self.batch = lks.Batch(self.stream)
         self.rounds = 0
@@ -113,11 +129,19 @@ class Server:
                     time.sleep(max(0.0, min(0.01, pending[0].arrival - (time.perf_counter() - t0))))
                 continue
             running = [a for a in active if not a.done]
+            if running and self.fill_cells > 0:
+                running.sort(key=lambda a: a.remaining)
+                acc, k = 0, 0
+                while k < len(running) and (k == 0 or acc < self.fill_cells):
+                    acc += running[k].cells
+                    k += 1
+                running = running[:k]
             if running:
                 flags = self.batch.round([a.solver for a in running])
                 self.rounds += 1
                 for a, f in zip(running, flags):
                     a.done = bool(f)
+                    a.rounds += 1
             # retire completed jobs without waiting on the stream
             for a in list(active):
                 if a.done and a.solver.poll():

@@ -97,3 +97,20 @@ def test_server_admission_by_budget():
     assert [r.status for r in res] == ["ok"] * 3
     assert srv.admission_waits > 0
     assert srv.peak_used <= need + 1
+
+
+def test_server_shortest_work_first_bitwise():
+    """With fill_cells set, jobs skip rounds while shorter ones advance; every result is still
+    bitwise the one the job gets through the single-job entry points."""
+    from paper_2506_23895_amd.server import Request, Server, serve_plain
+    cfgs = jobs()[:3]
+    reqs = [Request(k, 0.0, c, I.gamma_field(c["nd"], c["dim"], 40 + k)) for k, c in enumerate(cfgs)]
+    announce("server shortest work first")
+    srv = Server(fill_cells=1.0)  # one job per round
+    res = srv.serve(reqs)
+    srv.close()
+    ref = serve_plain(reqs)
+    for a, b in zip(res, ref):
+        assert a.status == b.status == "ok"
+        assert a.J == b.J, (a.rid, a.J, b.J)
+        assert np.array_equal(a.grad, b.grad), a.rid
