@@ -62,7 +62,8 @@ enum { LKS_W_COS4 = 0, LKS_W_LIN = 1 };
 /* boundary kinds, applied face by face in the order x-, x+, y-, y+, z-, z+ (a later face wins
  * at shared edges).  With s the next node inward from a face node:
  *   VELOCITY / NOSLIP : u = u_bar, rho = rho(s)
- *   ZERO_GRADIENT     : rho = rho(s), u = u(s)
+ *   ZERO_GRADIENT     : rho = rho_bar, u = u(s)  (outflow: du/dn = 0 with the pressure level
+ *                       held at rho_bar, the paper's Eq. bc_rho; rho_bar > 0 is required)
  *   PRESSURE          : rho = rho_bar, normal u = normal u(s), tangential u = u_bar
  *   PERIODIC          : both faces of the axis must be PERIODIC */
 enum { LKS_BC_PERIODIC = 0, LKS_BC_VELOCITY = 1, LKS_BC_PRESSURE = 2, LKS_BC_ZERO_GRADIENT = 3,
@@ -81,7 +82,7 @@ enum { LKS_F32 = 0, LKS_F64 = 1 };
 /* ---- descriptor ------------------------------------------------------------------------- */
 typedef struct {
     int kind;       /* LKS_BC_* */
-    double rho;     /* rho_bar (PRESSURE) */
+    double rho;     /* rho_bar (PRESSURE, ZERO_GRADIENT) */
     double u[3];    /* u_bar (VELOCITY, NOSLIP; tangential part for PRESSURE) */
 } lks_bc;
 

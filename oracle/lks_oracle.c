@@ -313,7 +313,9 @@ int or_transfer_T(const or_desc *d, int n, const double *kbar, double *G) {
  * directly).  Faces are applied in the order x-, x+, y-, y+, z-, z+, so a later face wins at
  * shared edges and corners.  On each face node p, with s = the next node inward:
  *   VELOCITY / NOSLIP: u = u_bar, rho = rho(s)
- *   ZERO_GRADIENT    : rho = rho(s), u = u(s)
+ *   ZERO_GRADIENT    : rho = rho_bar, u = u(s)   (outflow: zero normal gradient of u with the
+ *                      pressure level held by Eq. bc_rho; copying rho too leaves the mean
+ *                      pressure free and a channel then gains mass every step)
  *   PRESSURE         : rho = rho_bar, normal u = normal u(s), tangential u = u_bar tangential
  * ------------------------------------------------------------------------------------------ */
 static void face_nodes_apply(const or_desc *d, const grid_t *g, int f, double *rho, double *u,
@@ -335,7 +337,7 @@ static void face_nodes_apply(const or_desc *d, const grid_t *g, int f, double *r
                 for (int b = 0; b < g->dim; ++b) u[b * g->nc + idx] = d->bc_u[f][b];
                 break;
             case OR_BC_ZERO_GRADIENT:
-                rho[idx] = rho[si];
+                rho[idx] = d->bc_rho[f];
                 for (int b = 0; b < g->dim; ++b) u[b * g->nc + idx] = u[b * g->nc + si];
                 break;
             case OR_BC_PRESSURE:
@@ -353,7 +355,6 @@ static void face_nodes_apply(const or_desc *d, const grid_t *g, int f, double *r
                 rho[si] += rho[idx];
                 break;
             case OR_BC_ZERO_GRADIENT:
-                rho[si] += rho[idx];
                 for (int b = 0; b < g->dim; ++b) u[b * g->nc + si] += u[b * g->nc + idx];
                 break;
             case OR_BC_PRESSURE:

@@ -60,7 +60,7 @@ typedef struct {
     double kappa_max, q;
     int weight;              /* transfer kernel w */
     int bc_kind[6];          /* faces x-, x+, y-, y+, z-, z+ */
-    double bc_rho[6];
+    double bc_rho[6];        /* rho_bar of PRESSURE and ZERO_GRADIENT faces */
     double bc_u[6][3];
     double rho0, u0[3];      /* uniform initial state unless the fields below are given */
     const double *rho_init;  /* [ncell] or NULL */

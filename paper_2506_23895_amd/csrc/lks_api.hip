@@ -108,9 +108,13 @@ int plan(const lks_desc *d, Layout &L, std::string *err) {
         if (d->n[a] > (1 << 20) || d->nd[a] < 1 || d->nd[a] > (1 << 20))
             return fail(err, LKS_EINVAL, "grid extent out of range");
         g.n[a] = d->n[a];
-        for (int s = 0; s < 2; ++s)
-            if (!std::isfinite(d->bc[2 * a + s].rho) || !finite3(d->bc[2 * a + s].u))
+        for (int s = 0; s < 2; ++s) {
+            const lks_bc &bf = d->bc[2 * a + s];
+            if (!std::isfinite(bf.rho) || !finite3(bf.u))
                 return fail(err, LKS_EINVAL, "non-finite boundary value");
+            if ((bf.kind == LKS_BC_PRESSURE || bf.kind == LKS_BC_ZERO_GRADIENT) && !(bf.rho > 0.0))
+                return fail(err, LKS_EINVAL, "PRESSURE and ZERO_GRADIENT faces need rho_bar > 0");
+        }
     }
     const lks_objective &ob = d->objective;
     if (ob.kind != LKS_OBJ_NONE) {

@@ -258,7 +258,7 @@ __device__ __forceinline__ void transfer_box(const Design<T> &des, const StepMot
 // component either survives every face of p's chain (copied from s) or is fixed by the latest
 // face of the chain that prescribes it.  comp 0 = rho, comp 1 + b = u_b.
 __device__ __forceinline__ bool bc_copies(int kind, int comp, int axis) {
-    if (comp == 0) return kind == BC_VELOCITY || kind == BC_NOSLIP || kind == BC_ZERO_GRADIENT;
+    if (comp == 0) return kind == BC_VELOCITY || kind == BC_NOSLIP;
     return kind == BC_ZERO_GRADIENT || (kind == BC_PRESSURE && comp - 1 == axis);
 }
 
