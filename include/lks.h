@@ -151,13 +151,16 @@ void lks_destroy(lks_ctx *c);
  * and u_S at t_n, the LKS pull, the VPM force update and the boundary conditions, with the
  * objective accumulated in FP64 over the window.  gamma: [nd] in the context precision (float or
  * double), host or device memory per io_on_device, read before return.  *J receives the
- * objective (host).  Replaces any previous trajectory.  LKS_ENONFINITE if the final state holds
- * a NaN/Inf. */
+ * objective (host).  Replaces any previous trajectory.  The state is scanned for NaN/Inf after
+ * every 64th step and after the last: LKS_ENONFINITE if a scan finds one, and lks_last_error then
+ * names the first scanned step at which it was seen. */
 int lks_forward(lks_ctx *c, const void *gamma, double *J);
 
 /* Algorithm 2: the exact reverse sweep against the last forward, restoring each checkpointed
  * segment and recomputing it before its reverse steps, accumulating G(xi) = sum_n sum_x
- * W_n(x, xi) kappa_bar^n(x) in FP64.  LKS_ESTATE if no forward has run. */
+ * W_n(x, xi) kappa_bar^n(x) in FP64.  LKS_ESTATE if no forward has run.  The adjoint state is
+ * scanned for NaN/Inf after the reverse step of every n = 1 (mod 64), and G at the end:
+ * LKS_ENONFINITE if either holds one (lks_last_error names the latest reverse step seen). */
 int lks_adjoint(lks_ctx *c);
 
 /* dJ/dgamma = I'(gamma) * G on the design grid, [nd] in the context precision, host or device
@@ -205,7 +208,9 @@ const char *lks_batch_error(const lks_batch *b);
 /* 1 if context c's evaluation has completed on the device, 0 if not yet (never blocks). */
 int lks_poll(lks_ctx *c);
 
-/* Wait for context c's evaluation and return J (host); dJdgamma is then complete. */
+/* Wait for context c's evaluation and return J (host); dJdgamma is then complete.
+ * LKS_ENONFINITE if a scan of the forward state, the adjoint state or G found a NaN/Inf (the same
+ * scans as lks_forward and lks_adjoint). */
 int lks_finish(lks_ctx *c, double *J);
 
 /* Static description of the last failure of c (or of the last failed lks_create when c is

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -623,6 +624,52 @@ int copy_fields(lks_ctx *c, T *dst, const T *src, int nfields, hipStream_t s = n
     return LKS_OK;
 }
 
+// Non-finite guard: flag[0] = first forward step whose state held a NaN/Inf (INT_MAX: none),
+// flag[1] = largest n whose reverse step produced a non-finite adjoint state (0: none), flag[2] = 1
+// if G held a NaN/Inf.  Filled by kernels (no memset node), so the sequence stays capturable.
+int reset_flags(lks_ctx *c, bool fwd, hipStream_t s) {
+    if (fwd) HIPCHK(c, lks::launch_fill<int>(c->flag, INT_MAX, 1, s));
+    HIPCHK(c, lks::launch_fill<int>(c->flag + 1, 0, 2, s));
+    return LKS_OK;
+}
+
+bool scan_fwd_step(const lks_ctx *c, int n) { return n % lks::kScanEvery == 0 || n == c->d.nsteps; }
+bool scan_adj_step(int n) { return (n - 1) % lks::kScanEvery == 0; }
+
+// scan the state a forward step wrote (rho - 1 and the dim velocity fields, each run contiguous)
+template <typename T>
+int scan_fwd(lks_ctx *c, const lks::FwdArgs<T> &a, int n, hipStream_t s) {
+    HIPCHK(c, lks::launch_scan<T>(a.rout, c->L.F, a.uout[0], (long long)c->d.dim * c->L.F, n, c->flag, 0, s));
+    return LKS_OK;
+}
+
+template <typename T>
+int scan_adj(lks_ctx *c, const lks::AdjArgs<T> &a, int n, hipStream_t s) {
+    HIPCHK(c, lks::launch_scan<T>(a.Pout, c->L.F, a.Vout[0], (long long)c->d.dim * c->L.F, n, c->flag + 1, 1, s));
+    return LKS_OK;
+}
+
+int nonfinite_error(lks_ctx *c, const int f[3]) {
+    char buf[256];
+    if (f[0] != INT_MAX) {
+        const int prev = f[0] == c->d.nsteps && f[0] % lks::kScanEvery ? f[0] - f[0] % lks::kScanEvery
+                                                                       : f[0] - lks::kScanEvery;
+        std::snprintf(buf, sizeof buf,
+                      "non-finite forward state first seen after step %d (scanned every %d steps; finite "
+                      "after step %d)", f[0], lks::kScanEvery, prev > 0 ? prev : 0);
+    } else if (f[1] != 0) {
+        std::snprintf(buf, sizeof buf,
+                      "non-finite adjoint state first seen after the reverse step of n = %d (scanned every "
+                      "%d steps)", f[1], lks::kScanEvery);
+    } else if (f[2] != 0) {
+        std::snprintf(buf, sizeof buf, "non-finite value in the design sensitivity G");
+    } else {
+        return LKS_OK;
+    }
+    c->err = buf;
+    return LKS_ENONFINITE;
+}
+
 template <typename T>
 int forward_impl(lks_ctx *c, const void *gamma, double *J) {
     const Layout &L = c->L;
@@ -635,6 +682,7 @@ int forward_impl(lks_ctx *c, const void *gamma, double *J) {
                                          c->d.interp == LKS_INTERP_PAPER ? 0 : 1,
                                          c->d.kappa_max, c->d.q, c->stream));
     HIPCHK(c, lks::launch_fill<double>(c->jn, 0.0, N + 1, c->stream));
+    if ((rc = reset_flags(c, true, c->stream))) return rc;
 
     Fields<T> st[2] = {state_fields<T>(c, c->state), state_fields<T>(c, c->field(c->state, 1 + D))};
     {
@@ -696,6 +744,7 @@ int forward_impl(lks_ctx *c, const void *gamma, double *J) {
             }
         }
         if ((rc = launch_fwd_dev<T>(c, dfa + (n - 1), hfa[n - 1].mode, c->stream))) return rc;
+        if (scan_fwd_step(c, n) && (rc = scan_fwd<T>(c, hfa[n - 1], n, c->stream))) return rc;
         if (const int na = reduce_from(c, n))  // j^na .. j^n, each in block order
             HIPCHK(c, lks::launch_reduce_steps(c->partials, L.max_blocks, L.max_blocks, na, n, c->obj_scale,
                                                c->jn, c->stream));
@@ -712,22 +761,17 @@ int forward_impl(lks_ctx *c, const void *gamma, double *J) {
         }
         if ((rc = copy_fields<T>(c, fin.r, st[cur].r, 1))) return rc;
         if ((rc = copy_fields<T>(c, fin.u[0], ul[0], D))) return rc;
-        HIPCHK(c, lks::launch_fill<int>(c->flag, 0, 1, c->stream));
-        HIPCHK(c, lks::launch_nonfinite<T>(fin.r, (long long)(1 + D) * L.F, c->flag, c->stream));
     }
     std::vector<double> jn(N + 1);
-    int flag = 0;
+    int flag[3] = {0, 0, 0};
     HIPCHK(c, hipMemcpyAsync(jn.data(), c->jn, (N + 1) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(flag, c->flag, sizeof flag, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if ((rc = flush_timing(c))) return rc;
     double acc = 0.0;
     for (int n = 0; n <= N; ++n) acc += jn[n];
     if (J) *J = acc;
-    if (flag) {
-        c->err = "non-finite value in the final state";
-        return LKS_ENONFINITE;
-    }
+    if ((rc = nonfinite_error(c, flag))) return rc;
     c->have_fwd = true;
     return LKS_OK;
 }
@@ -840,6 +884,7 @@ int adjoint_impl(lks_ctx *c) {
     const auto *dsa = reinterpret_cast<const lks::SensArgs<T> *>(reinterpret_cast<const char *>(daa) + (size_t)N * sizeof(lks::AdjArgs<T>));
     HIPCHK(c, lks::launch_fill<T>(ad.r, T(0), (long long)(1 + D) * L.F, c->stream));
     HIPCHK(c, lks::launch_fill<double>(c->G, 0.0, L.nd, c->stream));
+    if ((rc = reset_flags(c, false, c->stream))) return rc;
     hipStream_t sr = c->stream2 ? c->stream2 : c->stream;  // recompute stream
     if (S > 1 && c->stream2) {  // stream2 starts after everything enqueued so far
         HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
@@ -869,14 +914,19 @@ int adjoint_impl(lks_ctx *c) {
             if (D == 2) rc = launch_adj_fused<T>(c, daa + (n - 1), aa[n - 1]);
             else rc = launch_adj_dev<T>(c, daa + (n - 1), dsa + (n - 1));
             if (rc) return rc;
+            if (scan_adj_step(n) && (rc = scan_adj<T>(c, aa[n - 1], n, c->stream))) return rc;
         }
         c->overlap = false;
         if (sr != c->stream) HIPCHK(c, hipEventRecord(c->ev_adj, c->stream));
     }
     if (D == 2 && (rc = launch_sens_dev<T>(c, dsa))) return rc;  // gather of step 1
+    HIPCHK(c, lks::launch_scan<double>(c->G, L.nd, nullptr, 0, 1, c->flag + 2, 1, c->stream));
+    int flag[3] = {INT_MAX, 0, 0};
+    HIPCHK(c, hipMemcpyAsync(flag + 1, c->flag + 1, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (sr != c->stream) HIPCHK(c, hipStreamSynchronize(sr));
     if ((rc = flush_timing(c))) return rc;
+    if ((rc = nonfinite_error(c, flag))) return rc;
     c->have_adj = true;
     return LKS_OK;
 }
@@ -1026,6 +1076,12 @@ struct RoundLists {
         int na, nb;
     };
     std::vector<Reduce> red;  // objective rows to reduce after this round's forward launches
+    struct Scan {
+        lks_ctx *c;
+        const T *p, *q;
+        int n, keep_max;
+    };
+    std::vector<Scan> scans;  // non-finite guards after this round's stencil launches
 };
 
 int list_of(const lks_ctx *c) { return c->d.dim == 2 ? 0 : (c->d.lattice == LKS_D3Q19 ? 1 : 2); }
@@ -1046,6 +1102,7 @@ int begin_impl(lks_ctx *c, const void *gamma, void *out) {
                                          c->d.interp == LKS_INTERP_PAPER ? 0 : 1,
                                          c->d.kappa_max, c->d.q, c->stream));
     HIPCHK(c, lks::launch_fill<double>(c->jn, 0.0, c->d.nsteps + 1, c->stream));
+    if (int rc = reset_flags(c, true, c->stream)) return rc;
     Fields<T> st = state_fields<T>(c, c->state);
     lks::InitArgs<T> ia{};
     ia.g = L.g;
@@ -1109,6 +1166,7 @@ int plan_step(lks_ctx *c, RoundLists<T> &R, int *rc) {
         R.fwd[li].push_back(make_fwd_args<T>(c, n, st[cs.cur].r, uin, st[1 - cs.cur].r, uout, fwd_loc<T>(c, n),
                                              n < N ? fwd_loc<T>(c, n + 1) : nullptr, true));
         R.ftiles[li].push_back(fwd_tiles(c, R.fwd[li].back().mode));
+        if (scan_fwd_step(c, n)) R.scans.push_back({c, R.fwd[li].back().rout, R.fwd[li].back().uout[0], n, 0});
         if (const int na = reduce_from(c, n)) R.red.push_back({c, na, n});
         cs.cur = 1 - cs.cur;
         cs.n = n + 1;
@@ -1161,6 +1219,7 @@ int plan_step(lks_ctx *c, RoundLists<T> &R, int *rc) {
         if (cs.ready <= cs.seg) {
             const int n = cs.n, j = n - cs.seg * K;
             R.adj[li].push_back(make_adj_args<T>(c, n, j, cs.acur));
+            if (scan_adj_step(n)) R.scans.push_back({c, R.adj[li].back().Pout, R.adj[li].back().Vout[0], n, 1});
             R.atiles[li].push_back(adj_tiles(c));
             R.ablk[li].push_back((L.ncell + lks::kBlockHost - 1) / lks::kBlockHost);
             R.sens.push_back(make_sens_args<T>(c, n));
@@ -1189,10 +1248,7 @@ int end_forward(lks_ctx *c) {
     int rc;
     if ((rc = copy_fields<T>(c, fin.r, st.r, 1))) return rc;
     if ((rc = copy_fields<T>(c, fin.u[0], ul[0], D))) return rc;
-    HIPCHK(c, lks::launch_fill<int>(c->flag, 0, 1, c->stream));
-    HIPCHK(c, lks::launch_nonfinite<T>(fin.r, (long long)(1 + D) * L.F, c->flag, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->jn_host, c->jn, (N + 1) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->flag_host, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     c->cs.phase = PH_ADJ_BEGIN;
     return LKS_OK;
 }
@@ -1200,6 +1256,8 @@ int end_forward(lks_ctx *c) {
 template <typename T>
 int end_reverse(lks_ctx *c) {
     HIPCHK(c, lks::launch_sens_finish<T>(c->kprime, c->G, reinterpret_cast<T *>(c->out_dev), c->L.nd, c->stream));
+    HIPCHK(c, lks::launch_scan<double>(c->G, c->L.nd, nullptr, 0, 1, c->flag + 2, 1, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->flag_host, c->flag, 3 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipEventRecord(c->done_ev, c->stream));
     c->cs.phase = PH_DONE;
     return LKS_OK;
@@ -1327,6 +1385,14 @@ int round_impl(lks_batch *b, lks_ctx *const *cs, int n, int *done) {
     for (const auto &r : R.red) {
         hipError_t e = lks::launch_reduce_steps(r.c->partials, r.c->L.max_blocks, r.c->L.max_blocks, r.na, r.nb,
                                                 r.c->obj_scale, r.c->jn, b->stream);
+        if (e != hipSuccess) {
+            b->err = hipGetErrorString(e);
+            return LKS_EDEVICE;
+        }
+    }
+    for (const auto &sc : R.scans) {
+        hipError_t e = lks::launch_scan<T>(sc.p, sc.c->L.F, sc.q, (long long)sc.c->d.dim * sc.c->L.F, sc.n,
+                                           sc.c->flag + sc.keep_max, sc.keep_max, b->stream);
         if (e != hipSuccess) {
             b->err = hipGetErrorString(e);
             return LKS_EDEVICE;
@@ -1567,7 +1633,7 @@ int lks_begin(lks_ctx *c, const void *gamma, void *dJdgamma) {
     if (c->cs.phase != 0 && c->cs.phase != 6) return set_err(c, LKS_ESTATE, "an evaluation is in flight");
     if (!c->jn_host) {
         if (hipHostMalloc(reinterpret_cast<void **>(&c->jn_host), (c->d.nsteps + 1) * sizeof(double), 0) != hipSuccess ||
-            hipHostMalloc(reinterpret_cast<void **>(&c->flag_host), sizeof(int), 0) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void **>(&c->flag_host), 3 * sizeof(int), 0) != hipSuccess ||
             hipEventCreateWithFlags(&c->done_ev, hipEventDisableTiming) != hipSuccess)
             return set_err(c, LKS_ENOMEM, "pinned host allocation failed");
     }
@@ -1620,10 +1686,7 @@ int lks_finish(lks_ctx *c, double *J) {
     for (int n = 0; n <= c->d.nsteps; ++n) acc += c->jn_host[n];
     if (J) *J = acc;
     c->cs.phase = 0;
-    if (*c->flag_host) {
-        c->err = "non-finite value in the final state";
-        return LKS_ENONFINITE;
-    }
+    if (int rc = nonfinite_error(c, c->flag_host)) return rc;
     c->have_fwd = c->have_adj = true;
     return LKS_OK;
 }

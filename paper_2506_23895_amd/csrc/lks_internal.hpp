@@ -151,8 +151,13 @@ hipError_t launch_sens_finish(const double *kprime, const double *G, T *out, lon
                               hipStream_t s);
 template <typename T>
 hipError_t launch_fill(T *p, T v, long long count, hipStream_t s);
+// a NaN/Inf among p[0, np) and q[0, nq) sets *flag = min(*flag, step) (keep_max = 0) or
+// max(*flag, step) (keep_max = 1)
 template <typename T>
-hipError_t launch_nonfinite(const T *p, long long count, int *flag, hipStream_t s);
+hipError_t launch_scan(const T *p, long long np, const T *q, long long nq, int step, int *flag, int keep_max,
+                       hipStream_t s);
+// the state of a sweep is scanned for NaN/Inf after every kScanEvery-th step (and the last)
+constexpr int kScanEvery = 64;
 // jn[n] = scale * sum_{b < nblocks} partials[(n - n0) * stride + b] for n in [n0, n1]
 hipError_t launch_reduce_steps(const double *partials, long long stride, long long nblocks, int n0,
                                int n1, double scale, double *jn, hipStream_t s);

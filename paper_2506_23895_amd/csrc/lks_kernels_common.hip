@@ -4,7 +4,7 @@
 //   sens gather   G(xi) += sum_x W_n(x - x_ref(xi)) kappa_bar^n(x): the transpose of the transfer
 //                 as a gather onto each design node (one thread per design node, no atomics)
 //   sens finish   dJ/dgamma = I'(gamma) G (Sec. 2.4, sensitivity pulled back to the design grid)
-//   fill, non-finite scan
+//   fill, non-finite scans (the whole state every few steps, recording the step of the first bad one)
 #include "lks_device.hpp"
 
 namespace lks {
@@ -77,10 +77,19 @@ __global__ __launch_bounds__(kBlock) void k_fill(T *p, T v, long long count) {
     if (i < count) p[i] = v;
 }
 
+// Elements [0, np) of p then [0, nq) of q; a NaN/Inf records `step` in *flag: the smallest such
+// step (keep_max = 0, forward sweep) or the largest (keep_max = 1, reverse sweep).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_nonfinite(const T *p, long long count, int *flag) {
+__global__ __launch_bounds__(kBlock) void k_scan(const T *p, long long np, const T *q, long long nq, int step,
+                                                 int *flag, int keep_max) {
     const long long i = blockIdx.x * (long long)kBlock + threadIdx.x;
-    if (i < count && !isfinite(p[i])) atomicOr(flag, 1);
+    bool bad = false;
+    if (i < np) bad = !isfinite(p[i]);
+    else if (i - np < nq) bad = !isfinite(q[i - np]);
+    if (bad) {
+        if (keep_max) atomicMax(flag, step);
+        else atomicMin(flag, step);
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_reduce_steps(const double *partials, long long stride,
@@ -135,9 +144,10 @@ hipError_t launch_fill(T *p, T v, long long count, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_nonfinite(const T *p, long long count, int *flag, hipStream_t s) {
-    if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_nonfinite<T>, grid1(count), dim3(kBlock), 0, s, p, count, flag);
+hipError_t launch_scan(const T *p, long long np, const T *q, long long nq, int step, int *flag, int keep_max,
+                       hipStream_t s) {
+    if (np + nq <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scan<T>, grid1(np + nq), dim3(kBlock), 0, s, p, np, q, nq, step, flag, keep_max);
     return hipGetLastError();
 }
 
@@ -158,7 +168,8 @@ hipError_t launch_reduce_steps(const double *partials, long long stride, long lo
     template hipError_t launch_sens_finish<T>(const double *, const double *, T *, long long,     \
                                               hipStream_t);                                       \
     template hipError_t launch_fill<T>(T *, T, long long, hipStream_t);                           \
-    template hipError_t launch_nonfinite<T>(const T *, long long, int *, hipStream_t);
+    template hipError_t launch_scan<T>(const T *, long long, const T *, long long, int, int *, int, \
+                                       hipStream_t);
 LKS_INST(float)
 LKS_INST(double)
 template hipError_t launch_fill<unsigned int>(unsigned int *, unsigned int, long long, hipStream_t);
