@@ -213,8 +213,28 @@ int lks_poll(lks_ctx *c);
  * scans as lks_forward and lks_adjoint). */
 int lks_finish(lks_ctx *c, double *J);
 
-/* Static description of the last failure of c (or of the last failed lks_create when c is
- * NULL), and of a return code. */
+/* ---- forward sweep without device allocation ------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the forward sweep of lks_forward for descriptor d, with
+ * every buffer the kernels need beyond the caller's (state ping-pong, X^0, X^N, footprint ring,
+ * design arrays, objective partials and per-step values, argument blocks) carved out of one static
+ * device array of LKS_NOALLOC_SCRATCH_BYTES bytes, which each device the library runs on holds
+ * until the process ends.  No hipMalloc, hipFree or other allocating routine is called.
+ *   gamma   [nd] design field in the descriptor's precision (host or device memory);
+ *   J       host, receives the objective (may be NULL);
+ *   drho, u X^N as rho - 1 [ncell] and u [dim][ncell], component-major, descriptor precision,
+ *           host or device memory (either may be NULL).
+ * The results are those of lks_create + lks_forward + lks_read_state(FINAL) on the same inputs.
+ * d->checkpoint_every and d->io_on_device are ignored; the work runs on d->stream, which is
+ * synchronised before return.  LKS_EINVAL if the workload needs more scratch than the array holds
+ * (lks_last_error(NULL) says how much); LKS_ENONFINITE as for lks_forward.  Every call on one
+ * device shares that device's array and leaves its contents behind: calls that overlap on one
+ * device (two host threads, or two streams) race, so serialise them. */
+#define LKS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int lks_forward_noalloc(const lks_desc *d, const void *gamma, double *J, void *drho, void *u);
+
+/* Static description of the last failure of c (or, when c is NULL, of the last failed
+ * lks_create or lks_forward_noalloc of the calling thread), and of a return code. */
 const char *lks_last_error(const lks_ctx *c);
 const char *lks_strerror(int code);
 

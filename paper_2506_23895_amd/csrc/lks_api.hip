@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1037,6 +1038,165 @@ int create_impl(const lks_desc *d, lks_ctx *c) {
     return LKS_OK;
 }
 
+// ---- forward sweep without device allocation -------------------------------------------------
+// Every buffer the forward kernels use beyond the caller's gamma and outputs is carved out of one
+// static device array (`scratch`).  In host code the array's name is only a stand-in for the
+// symbol: its device address is taken with hipGetSymbolAddress once per device, with that device
+// current, and only that address is ever handed to kernels or copies.
+constexpr size_t kScratchBytes = LKS_NOALLOC_SCRATCH_BYTES;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// device address of this device's copy of `scratch` (set up on the first call on the device)
+int scratch_address(void **out, std::string *err) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(err, LKS_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(err, LKS_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(err, LKS_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return LKS_OK;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+template <typename T>
+int forward_noalloc_impl(const lks_desc *d, const void *gamma, double *J, void *drho, void *u,
+                         std::string *err) {
+    lks_ctx c;  // host bookkeeping only: its device pointers all point into the scratch
+    int rc = plan(d, c.L, err);
+    if (rc) return rc;
+    Layout &L = c.L;
+    const int D = d->dim, N = d->nsteps;
+    // the forward sweep alone: X^0 is the only checkpoint and no trajectory is stored
+    L.fwd_only = true;
+    L.K = N;
+    L.S = 1;
+    L.banks = 1;
+    const size_t e = L.esz, nf = 1 + D, fb = (size_t)L.F * e;
+    const bool has_mask = d->objective.kind != LKS_OBJ_NONE && d->objective.mask;
+    struct Part {
+        char **dst;
+        size_t bytes;
+    };
+    char *argdev = nullptr, *counter = nullptr, *kprime = nullptr, *jn = nullptr, *partials = nullptr;
+    const size_t args_bytes = (size_t)(N + 1) * sizeof(lks::FwdArgs<T>);
+    const Part parts[] = {
+        {&c.state, 2 * nf * fb},
+        {&c.ckpt, nf * fb},
+        {&c.fin, nf * fb},
+        {&c.xring, L.b_xring},
+        {&c.gamma, (size_t)L.nd * e},
+        {&c.kref, (size_t)L.nd * e},
+        {&kprime, (size_t)L.nd * 8},
+        {&jn, (size_t)(N + 1) * 8},
+        {&partials, (size_t)L.prow * L.max_blocks * 8},
+        {&counter, 64},
+        {&c.kstatic, d->kappa_static ? fb : 0},
+        {reinterpret_cast<char **>(&c.mask), has_mask ? (size_t)L.F : 0},
+        {&c.init, (d->rho_init || d->u_init) ? nf * fb : 0},
+        {&argdev, args_bytes + 256},  // + tile0
+    };
+    size_t need = 0;
+    for (const Part &pt : parts) need += align256(pt.bytes);
+    if (need > kScratchBytes)
+        return fail(err, LKS_EINVAL,
+                    "this forward sweep needs " + std::to_string(need) + " bytes of scratch; the static scratch "
+                    "holds " + std::to_string(kScratchBytes) + " (use lks_create / lks_forward)");
+    void *base = nullptr;
+    if ((rc = scratch_address(&base, err))) return rc;
+    size_t off = 0;
+    for (const Part &pt : parts) {
+        *pt.dst = pt.bytes ? static_cast<char *>(base) + off : nullptr;
+        off += align256(pt.bytes);
+    }
+    c.kprime = reinterpret_cast<double *>(kprime);
+    c.jn = reinterpret_cast<double *>(jn);
+    c.partials = reinterpret_cast<double *>(partials);
+    c.counter = reinterpret_cast<unsigned int *>(counter);
+    c.flag = reinterpret_cast<int *>(counter + 32);
+    c.argdev = argdev;
+    c.argcap = args_bytes;
+    c.tile0 = reinterpret_cast<long long *>(argdev + args_bytes);
+    std::vector<char> staging(args_bytes);  // host staging of the argument blocks
+    c.arghost = staging.data();
+    c.d = *d;
+    c.d.motion = nullptr;  // the plan holds every step's motion
+    c.stream = reinterpret_cast<hipStream_t>(d->stream);
+    hipError_t he = hipGetDevice(&c.dev);
+    if (he != hipSuccess) return fail(err, LKS_EDEVICE, hipGetErrorString(he));
+    // the scratch keeps the previous call's contents: clear what must start at zero (the padded
+    // row tails of the fields, which the kernels never write, the counters and the job table)
+    rc = LKS_OK;
+    auto check = [&](hipError_t x) {
+        if (x != hipSuccess && rc == LKS_OK) rc = fail(err, LKS_EDEVICE, hipGetErrorString(x));
+    };
+    check(lks::launch_fill<T>(reinterpret_cast<T *>(c.state), T(0), (long long)(2 * nf * L.F), c.stream));
+    check(lks::launch_fill<int>(reinterpret_cast<int *>(counter), 0, 16, c.stream));
+    check(lks::launch_fill<int>(reinterpret_cast<int *>(c.tile0), 0, 64, c.stream));
+    if (rc) return rc;
+    if (d->kappa_static) {
+        rc = upload_padded<T>(&c, c.kstatic, d->kappa_static, 1);
+        if (rc) return fail(err, rc, c.err);
+    }
+    if (d->rho_init || d->u_init) {
+        std::vector<double> h(nf * (size_t)L.ncell);
+        for (long long i = 0; i < L.ncell; ++i) h[i] = (d->rho_init ? d->rho_init[i] : d->rho0) - 1.0;
+        for (int k = 0; k < D; ++k)
+            for (long long i = 0; i < L.ncell; ++i)
+                h[(1 + k) * L.ncell + i] = d->u_init ? d->u_init[k * L.ncell + i] : d->u0[k];
+        rc = upload_padded<T>(&c, c.init, h.data(), (int)nf);
+        if (rc) return fail(err, rc, c.err);
+    }
+    long long mcount = L.ncell;
+    if (has_mask) {
+        std::vector<uint8_t> h(L.F, 0);
+        mcount = 0;
+        for (long long z = 0; z < L.g.n[2]; ++z)
+            for (long long y = 0; y < L.g.n[1]; ++y)
+                for (long long x = 0; x < L.g.n[0]; ++x) {
+                    const uint8_t v = d->objective.mask[x + L.g.n[0] * (y + L.g.n[1] * z)] ? 1 : 0;
+                    h[x + y * L.g.sy + z * L.g.sz] = v;
+                    mcount += v;
+                }
+        he = hipMemcpy(c.mask, h.data(), L.F, hipMemcpyHostToDevice);
+        if (he != hipSuccess) return fail(err, LKS_EDEVICE, hipGetErrorString(he));
+    }
+    c.d.rho_init = c.d.u_init = c.d.kappa_static = nullptr;
+    c.d.objective.mask = nullptr;
+    c.obj_scale = 1.0;
+    if (d->objective.normalize & LKS_NORM_TIME) c.obj_scale /= (double)(d->objective.n1 - d->objective.n0 + 1);
+    if (d->objective.normalize & LKS_NORM_MASK) c.obj_scale /= (double)std::max(1LL, mcount);
+
+    rc = forward_impl<T>(&c, gamma, J);
+    if (rc) return fail(err, rc, c.err);
+    const size_t rows = (size_t)L.g.n[1] * L.g.n[2];
+    if (drho) check(hipMemcpy2DAsync(drho, L.g.n[0] * e, c.fin, L.pitch * e, L.g.n[0] * e, rows,
+                                     hipMemcpyDefault, c.stream));
+    if (u)
+        for (int k = 0; k < D; ++k)
+            check(hipMemcpy2DAsync(static_cast<char *>(u) + (size_t)k * L.ncell * e, L.g.n[0] * e,
+                                   c.field(c.fin, 1 + k), L.pitch * e, L.g.n[0] * e, rows, hipMemcpyDefault,
+                                   c.stream));
+    check(hipStreamSynchronize(c.stream));
+    return rc;
+}
+
 }  // namespace
 
 // ================================ continuous batching ========================================
@@ -1507,6 +1667,20 @@ int lks_forward(lks_ctx *c, const void *gamma, double *J) {
         return c->L.esz == 8 ? forward_impl<double>(c, gamma, J) : forward_impl<float>(c, gamma, J);
     } catch (...) {
         return set_err(c, LKS_ENOMEM, "host exception in lks_forward");
+    }
+}
+
+int lks_forward_noalloc(const lks_desc *d, const void *gamma, double *J, void *drho, void *u) {
+    if (!d || !gamma) {
+        g_create_error = "descriptor or gamma is NULL";
+        return LKS_EINVAL;
+    }
+    try {
+        return d->precision == LKS_F64 ? forward_noalloc_impl<double>(d, gamma, J, drho, u, &g_create_error)
+                                       : forward_noalloc_impl<float>(d, gamma, J, drho, u, &g_create_error);
+    } catch (...) {
+        g_create_error = "host exception in lks_forward_noalloc";
+        return LKS_ENOMEM;
     }
 }
 

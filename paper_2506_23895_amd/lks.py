@@ -34,7 +34,7 @@ EXPORTS = ["lks_query_bytes", "lks_create", "lks_destroy", "lks_forward", "lks_a
            "lks_sensitivity", "lks_read_state", "lks_read_objective_steps", "lks_set_timing",
            "lks_kernel_timing", "lks_last_error", "lks_strerror", "lks_batch_create",
            "lks_batch_destroy", "lks_begin", "lks_batch_round", "lks_batch_error", "lks_poll",
-           "lks_finish"]
+           "lks_finish", "lks_forward_noalloc"]
 
 
 class LksBc(C.Structure):
@@ -112,6 +112,7 @@ def lib():
         L.lks_batch_error.restype = C.c_char_p
         L.lks_poll.argtypes = [P]
         L.lks_finish.argtypes = [P, C.POINTER(C.c_double)]
+        L.lks_forward_noalloc.argtypes = [C.POINTER(LksDesc), P, C.POINTER(C.c_double), P, P]
         _lib = L
     return _lib
 
@@ -184,6 +185,25 @@ def _check(rc: int, ctx=None):
     if rc != LKS_OK:
         msg = lib().lks_last_error(ctx).decode() if ctx is not None else lib().lks_last_error(None).decode()
         raise LksError(rc, msg or lib().lks_strerror(rc).decode())
+
+
+def _addr(x):
+    """Address of a torch tensor's or numpy array's data (None stays NULL)."""
+    if x is None:
+        return None
+    if hasattr(x, "data_ptr"):
+        return C.c_void_p(int(x.data_ptr()))
+    return C.c_void_p(x.ctypes.data)
+
+
+def forward_noalloc(cfg: dict, gamma, drho=None, u=None, stream: Optional[int] = None) -> float:
+    """lks_forward_noalloc: the forward sweep with every kernel buffer in the library's static
+    device scratch.  gamma [nd], drho [ncell] and u [dim, ncell] in the workload precision (torch
+    tensors or numpy arrays; the outputs may be None).  Returns J."""
+    h = _DescHolder(cfg, io_on_device=True, stream=stream)
+    J = C.c_double(0.0)
+    _check(lib().lks_forward_noalloc(C.byref(h.d), _addr(gamma), C.byref(J), _addr(drho), _addr(u)))
+    return J.value
 
 
 def query_bytes(cfg: dict, hbm_budget: int = 0) -> int:

@@ -228,6 +228,8 @@ hipError_t hipEventRecord(hipEvent_t e, hipStream_t s = nullptr);
 hipError_t hipEventSynchronize(hipEvent_t e);
 hipError_t hipEventQuery(hipEvent_t e);
 hipError_t hipEventElapsedTime(float *ms, hipEvent_t a, hipEvent_t b);
+#define HIP_SYMBOL(x) ((const void *)&(x))
+hipError_t hipGetSymbolAddress(void **p, const void *symbol);
 
 #define hipLaunchKernelGGL(kernel, grid, block, shmem, stream, ...)                                  \
     emu::run_launch([&]() { (kernel)(__VA_ARGS__); }, dim3(grid), dim3(block), (size_t)(shmem))
