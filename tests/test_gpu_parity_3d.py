@@ -72,6 +72,21 @@ CASES = {
         obj="DRAG", n=(40, 27, 21),
         bcs=[_bc("VELOCITY", 1.0, (0.03, 0, 0)), _bc("PRESSURE", 1.001, (0, 0.002, 0.001)),
              _bc("NOSLIP"), _bc("NOSLIP", 1.0, (0.01, 0, 0)), _bc("PERIODIC"), _bc("PERIODIC")]),
+    # the boundary ingredients of the walls-everywhere case, one configuration each (each cleared
+    # first by the host emulation of the kernels, tests/test_emu_bounds.py): a ZERO_GRADIENT z face
+    # under heave, a PRESSURE outlet with a tangential z value, heave with walls on every face
+    "d3q19_zg_zminus_heave_power": dict(
+        obj="POWER", motion="heave",
+        bcs=[_bc("VELOCITY", 1.0, (0.03, 0, 0)), _bc("ZERO_GRADIENT"), _bc("PERIODIC"), _bc("PERIODIC"),
+             _bc("ZERO_GRADIENT"), _bc("NOSLIP")]),
+    "d3q19_pressure_tangential_z_drag": dict(
+        obj="DRAG",
+        bcs=[_bc("VELOCITY", 1.0, (0.03, 0, 0)), _bc("PRESSURE", 1.001, (0, 0.002, 0.001)),
+             _bc("NOSLIP"), _bc("NOSLIP", 1.0, (0.01, 0, 0)), _bc("PERIODIC"), _bc("PERIODIC")]),
+    "d3q19_heave_walls_all_faces_torque": dict(
+        motion="heave",
+        bcs=[_bc("VELOCITY", 1.0, (0.03, 0, 0)), _bc("ZERO_GRADIENT"), _bc("NOSLIP"), _bc("NOSLIP"),
+             _bc("NOSLIP"), _bc("NOSLIP", 1.0, (0.0, 0.01, 0))]),
 }
 
 
