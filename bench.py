@@ -84,14 +84,26 @@ def bytes_per_lup(cfg: dict) -> dict:
     }
 
 
-def kernel_source_hash() -> str:
+_HASH_OVERRIDE = None
+
+
+def kernel_source_hash(read=None) -> str:
     """Hash of the device-code sources (the host runtime lks_api.hip is not part of it), with
-    comments and whitespace removed, so that documentation edits keep measured profiles valid."""
+    comments and whitespace removed, so that documentation edits keep measured profiles valid.
+    read(name) -> text reads another revision of the sources (default: the working tree)."""
     import re
+    if _HASH_OVERRIDE and read is None:
+        return _HASH_OVERRIDE
+    csrc = os.path.join(ROOT, "paper_2506_23895_amd", "csrc")
+    if read is None:
+        names = os.listdir(csrc)
+        read = lambda f: open(os.path.join(csrc, f)).read()  # noqa: E731
+    else:
+        names = read(None)
     h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2506_23895_amd", "csrc"))):
+    for f in sorted(names):
         if f.endswith((".hip", ".hpp")) and f != "lks_api.hip":
-            text = open(os.path.join(ROOT, "paper_2506_23895_amd", "csrc", f)).read()
+            text = read(f)
             text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
             text = re.sub(r"//[^\n]*", " ", text)
             h.update(f.encode() + b"\0" + " ".join(text.split()).encode())
@@ -117,6 +129,57 @@ def read_traffic(kernel: str, wl: str, per_launch_alg: float):
         return None
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+_SINGLE = r"""
+import sys, time, json
+sys.path.insert(0, {root!r})
+import numpy as np
+import lks_inputs as I
+from oracle import oracle as O
+sys.path.insert(0, {root!r})
+import bench
+cfg, gamma = bench.workload({wl!r}, 0)
+c = bench.sample_cfg(cfg, {steps})
+t0 = time.perf_counter()
+O.solve(c, gamma, grad=c["objective"]["kind"] != "NONE")
+print(json.dumps({{"seconds": time.perf_counter() - t0, "threads": O.num_threads()}}))
+"""
+
+
+def sample_cfg(cfg: dict, sample_steps: int) -> dict:
+    c = dict(cfg)
+    c["nsteps"] = sample_steps
+    c["motion"] = cfg["motion"][: sample_steps + 1]
+    ob = dict(cfg["objective"])
+    if ob["kind"] != "NONE":
+        ob["n1"] = min(ob["n1"], sample_steps)
+    c["objective"] = ob
+    return c
+
+
+def single_thread_rate(wl: str, cfg: dict, steps: int) -> dict:
+    """The same oracle in a child process restricted to one OpenMP thread (a shorter sample)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", _SINGLE.format(root=ROOT, wl=wl, steps=steps)], env=env,
+                         capture_output=True, text=True, timeout=600)
+    if out.returncode != 0:
+        return {"error": out.stderr[-300:]}
+    r = json.loads(out.stdout.strip().splitlines()[-1])
+    cells = int(np.prod(cfg["n"]))
+    return {"value": round(cells * steps / r["seconds"] / 1e6, 4), "unit": "MLUPS", "cores": r["threads"],
+            "sample": f"first {steps} steps, {r['seconds']:.1f} s"}
+
+
 def cpu_baseline(wl: str, cfg: dict, gamma: np.ndarray) -> dict:
     """The FP64 oracle as it stands, on a bounded sample of the same workload."""
     from oracle import oracle as O
@@ -133,10 +196,12 @@ def cpu_baseline(wl: str, cfg: dict, gamma: np.ndarray) -> dict:
     O.solve(c, gamma, grad=grad)
     dt = time.perf_counter() - t0
     cells = int(np.prod(c["n"]))
+    single_steps = {"c1": 100, "c2": 6, "c3": 12, "c4": 1}[wl]
     return {"value": round(cells * sample_steps / dt / 1e6, 4), "unit": "MLUPS",
-            "cores": O.num_threads(), "kind": "oracle",
+            "cores": O.num_threads(), "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"{'x'.join(str(v) for v in c['n'][:c['dim']])} grid, first {sample_steps} steps "
-                      f"{'forward + reverse' if grad else 'forward'}, FP64 C oracle, {dt:.1f} s"}
+                      f"{'forward + reverse' if grad else 'forward'}, FP64 C oracle, {dt:.1f} s",
+            "single_thread": single_thread_rate(wl, cfg, single_steps)}
 
 
 def served_leg(n_req: int, rate: float, seed: int = 5, fill_cells: float = 0.0) -> dict:
@@ -220,7 +285,7 @@ def pmc_summary(fetch_csv: str, write_csv: str, wl: str, nsteps: int) -> None:
         hbm = (kib["FETCH_SIZE"] * factor["FETCH_SIZE"] + kib["WRITE_SIZE"] * factor["WRITE_SIZE"]) * 1024
         alg = bpl[kind] * cells
         cmd = ("rocprofv3 --pmc {c} -d {d} -o {o} --output-format csv -- python3 bench.py "
-               f"--no-cpu-baseline --no-served --steps 1 --warmup 0 --workload {wl} "
+               f"--no-cpu-baseline --no-served --no-extra --steps 1 --warmup 0 --workload {wl} "
                f"--nsteps {nsteps} --calibrate-copy")
         out = [f"# HBM traffic per launch of {kind} ({', '.join(names)}) for the {cfg['name']} workload",
                "# commands (two passes, one counter each):"]
@@ -288,6 +353,94 @@ def trace_summary(prefix: str, log: str, plain_log: str, wl: str, cmd: str) -> N
     print("\n".join(out))
 
 
+def measure(cfg: dict, gamma: np.ndarray, wl: str, steps: int, warmup: int, timing_every: int,
+            variant: bool) -> dict:
+    """Warm up, then time `steps` whole evaluations (forward, and reverse + sensitivity when the
+    workload has an objective) with every input already in device memory."""
+    import torch
+    from paper_2506_23895_amd import lks
+    dev = torch.device("cuda:0")
+    tdtype = torch.float64 if cfg["precision"] == "F64" else torch.float32
+    g_dev = torch.from_numpy(gamma).to(dev, dtype=tdtype)
+    out = torch.empty_like(g_dev)
+    has_adj = cfg["objective"]["kind"] != "NONE"
+    cells = int(np.prod(cfg["n"]))
+    N = cfg["nsteps"]
+    print(f"[bench] workload {cfg['name']} cells={cells} steps={N} K={cfg['checkpoint_every']}",
+          flush=True)
+    solver = lks.Solver(cfg, io_on_device=True)
+
+    def one():
+        J = solver.forward(g_dev)
+        if has_adj:
+            solver.adjoint()
+            solver.sensitivity(out)
+        return J
+
+    for w in range(warmup):
+        J = one()
+        print(f"[bench] warmup {w} J={J:.6e}", flush=True)
+    solver.set_timing(timing_every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tf = 0.0
+    for k in range(steps):
+        a0 = time.perf_counter()
+        J = solver.forward(g_dev)
+        tf += time.perf_counter() - a0
+        if has_adj:
+            solver.adjoint()
+            solver.sensitivity(out)
+        print(f"[bench] step {k} J={J:.6e}", flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    value = cells * N * steps / dt / 1e6
+    finite = bool(torch.isfinite(out).all().item()) if has_adj else True
+
+    # live means: forward-sweep launches for fwd_step; reverse-sweep launches of the one segment
+    # that runs with no recompute beside it for adj_step and sens_gather
+    timing = {}
+    for kind, name in KINDS.items():
+        cnt, mean = solver.kernel_timing(kind)
+        timing[name] = {"samples": cnt, "mean_ms": mean}
+    solver.close()
+    K = cfg["checkpoint_every"] or N
+    S = (N + K - 1) // K
+    # forward-step launches: N in the forward sweep plus the recomputed segments (all but the last)
+    # (2D: the gather of each adjoint step rides in the next adjoint launch; only the last one
+    # is a launch of its own)
+    launches = {"fwd_step": N + ((S - 1) * K if has_adj else 0),
+                "adj_step": N if has_adj else 0,
+                "sens_gather": (N if cfg["dim"] == 3 else 1) if has_adj else 0}
+    tot = {k: launches[k] * timing[k]["mean_ms"] for k in launches}
+    dom = max(tot, key=tot.get)
+    bpl = bytes_per_lup(cfg)
+    alg = bpl.get(dom, 0) * cells
+    mean_s = timing[dom]["mean_ms"] / 1e3
+    achieved = alg / mean_s / 1e9 if mean_s > 0 else 0.0
+    # the committed counter summaries cover the workloads as stated, not their variants
+    traffic = None if variant else read_traffic(dom, wl, alg)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": dom, "alg_bytes_per_launch": alg, "mean_launch_ms": timing[dom]["mean_ms"]}
+    # whole evaluation at the algorithmic bytes of every launch it makes
+    eval_bytes = sum(launches[k] * bpl.get(k, 0) * cells for k in ("fwd_step", "adj_step"))
+    return {
+        "value": round(value, 1), "unit": "MLUPS", "ms_per_eval": round(dt / steps * 1e3, 3),
+        "config": {"workload": cfg["name"], "grid": list(cfg["n"][:cfg["dim"]]),
+                   "design": list(cfg["nd"][:cfg["dim"]]), "lattice": cfg["lattice"],
+                   "transfer": cfg["weight"], "precision": cfg["precision"],
+                   "time_steps": N, "checkpoint_every": cfg["checkpoint_every"],
+                   "objective": cfg["objective"]["kind"], "parallelism": "single GPU",
+                   "motion_period": STABLE_PERIOD.get(wl)},
+        "J": J, "sens_finite": finite, "fwd_ms_per_step": round(tf / steps * 1e3, 3),
+        "evals_per_s": round(steps / dt, 4) if has_adj else None,
+        "whole_eval_hbm_frac": round(eval_bytes * steps / dt / 1e9 / HBM_PEAK_GBS, 4),
+        "kernels": timing,
+        "roofline": roof,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -297,6 +450,7 @@ def main() -> int:
     ap.add_argument("--requests", type=int, default=12, help="served leg: number of requests")
     ap.add_argument("--rate", type=float, default=50.0, help="served leg: arrivals per second")
     ap.add_argument("--no-served", action="store_true", help="skip the served leg")
+    ap.add_argument("--no-extra", action="store_true", help="skip the c4 and c2 legs of the default line")
     ap.add_argument("--fill-cells", type=float, default=0.0,
                     help="served leg: cells per round, shortest remaining work first (0: every job)")
     ap.add_argument("--nsteps", type=int, default=0, help="override the time horizon (profiling)")
@@ -314,7 +468,23 @@ def main() -> int:
     ap.add_argument("--trace-summary", nargs=3, metavar=("PREFIX", "LOG", "PLAIN_LOG"),
                     help="write profiles/kernels_*.txt from a rocprofv3 kernel trace (CPU only)")
     ap.add_argument("--trace-command", default="", help="the profiled command, for the summary")
+    ap.add_argument("--source-rev", default="",
+                    help="summaries: git revision whose device sources were profiled (default: the "
+                         "hash in the profiled run's log, else the working tree)")
     args = ap.parse_args()
+    global _HASH_OVERRIDE
+    if args.source_rev:
+        import subprocess
+
+        def read(f, rev=args.source_rev):
+            path = "paper_2506_23895_amd/csrc"
+            if f is None:
+                out = subprocess.check_output(["git", "ls-tree", "--name-only", f"{rev}:{path}"], cwd=ROOT)
+                return out.decode().split()
+            return subprocess.check_output(["git", "show", f"{rev}:{path}/{f}"], cwd=ROOT).decode()
+        _HASH_OVERRIDE = kernel_source_hash(read)
+    elif args.trace_summary:
+        _HASH_OVERRIDE = _json_line(args.trace_summary[1]).get("kernel_source_hash") or None
     if args.pmc_summary:
         pmc_summary(*args.pmc_summary, args.workload, args.nsteps)
         return 0
@@ -364,87 +534,29 @@ def main() -> int:
         variant.append(args.transfer.lower())
     if variant:
         cfg["name"] += "_" + "_".join(variant)
-    tdtype = torch.float64 if cfg["precision"] == "F64" else torch.float32
-    g_dev = torch.from_numpy(gamma).to(dev, dtype=tdtype)
-    out = torch.empty_like(g_dev)
+    m = measure(cfg, gamma, args.workload, args.steps, args.warmup, args.timing_every, bool(variant))
     has_adj = cfg["objective"]["kind"] != "NONE"
-    cells = int(np.prod(cfg["n"]))
-    N = cfg["nsteps"]
-    print(f"[bench] workload {cfg['name']} cells={cells} steps={N} K={cfg['checkpoint_every']}",
-          flush=True)
-    solver = lks.Solver(cfg, io_on_device=True)
-
-    def one():
-        J = solver.forward(g_dev)
-        if has_adj:
-            solver.adjoint()
-            solver.sensitivity(out)
-        return J
-
-    for w in range(args.warmup):
-        J = one()
-        print(f"[bench] warmup {w} J={J:.6e}", flush=True)
-    solver.set_timing(args.timing_every)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    tf = 0.0
-    for k in range(args.steps):
-        a0 = time.perf_counter()
-        J = solver.forward(g_dev)
-        tf += time.perf_counter() - a0
-        if has_adj:
-            solver.adjoint()
-            solver.sensitivity(out)
-        print(f"[bench] step {k} J={J:.6e}", flush=True)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms = dt / args.steps * 1e3
-    value = cells * N * args.steps / dt / 1e6
-    finite = bool(torch.isfinite(out).all().item()) if has_adj else True
-
-    # live means: forward-sweep launches for fwd_step; reverse-sweep launches of the one segment
-    # that runs with no recompute beside it for adj_step and sens_gather
-    timing = {}
-    for kind, name in KINDS.items():
-        cnt, mean = solver.kernel_timing(kind)
-        timing[name] = {"samples": cnt, "mean_ms": mean}
-    K = cfg["checkpoint_every"] or N
-    S = (N + K - 1) // K
-    # forward-step launches: N in the forward sweep plus the recomputed segments (all but the last)
-    # (2D: the gather of each adjoint step rides in the next adjoint launch; only the last one
-    # is a launch of its own)
-    launches = {"fwd_step": N + ((S - 1) * K if has_adj else 0),
-                "adj_step": N if has_adj else 0,
-                "sens_gather": (N if cfg["dim"] == 3 else 1) if has_adj else 0}
-    tot = {k: launches[k] * timing[k]["mean_ms"] for k in launches}
-    dom = max(tot, key=tot.get)
-    bpl = bytes_per_lup(cfg)
-    alg = bpl.get(dom, 0) * cells
-    mean_s = timing[dom]["mean_ms"] / 1e3
-    achieved = alg / mean_s / 1e9 if mean_s > 0 else 0.0
-    # the committed counter summaries cover the workloads as stated, not their variants
-    traffic = None if variant else read_traffic(dom, args.workload, alg)
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": dom, "alg_bytes_per_launch": alg, "mean_launch_ms": timing[dom]["mean_ms"]}
     line = {
         "metric": METRIC if has_adj else "MLUPS fwd (D2Q9)",
-        "value": round(value, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
+        "value": m["value"], "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": m["ms_per_eval"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if cfg["precision"] == "F64" else "f32", "data": "synthetic",
-        "config": {"workload": cfg["name"], "grid": list(cfg["n"][:cfg["dim"]]),
-                   "design": list(cfg["nd"][:cfg["dim"]]), "lattice": cfg["lattice"],
-                   "transfer": cfg["weight"],
-                   "time_steps": N, "checkpoint_every": cfg["checkpoint_every"],
-                   "objective": cfg["objective"]["kind"], "parallelism": "single GPU",
-                   "motion_period": args.period or STABLE_PERIOD.get(args.workload)},
-        "J": J, "sens_finite": finite, "fwd_ms_per_step": round(tf / args.steps * 1e3, 3),
-        "evals_per_s": round(args.steps / dt, 4) if has_adj else None,
-        "kernels": timing,
-        "roofline": roof,
+        "config": dict(m["config"], motion_period=args.period or STABLE_PERIOD.get(args.workload)),
     }
-    solver.close()
+    line.update({k: v for k, v in m.items() if k not in ("value", "ms_per_eval", "config")})
+    line["kernel_source_hash"] = kernel_source_hash()
+    if args.workload == "c3" and not args.nsteps and not variant and not args.no_extra:
+        # the D2Q9 headline is C3; the D3Q19 half of the metric (C4) and the forward-only C2 ride
+        # in the same line, each with its own roofline, traffic and CPU baseline
+        for wl, steps in (("c4", 2), ("c2", 2)):
+            c2cfg, c2g = workload(wl, 0)
+            print(f"[bench] {wl} leg", flush=True)
+            sub = measure(c2cfg, c2g, wl, steps, 1, args.timing_every, False)
+            sub["steps"], sub["warmup"] = steps, 1
+            if not args.no_cpu_baseline:
+                sub["cpu_baseline"] = cpu_baseline(wl, c2cfg, c2g)
+            line[wl] = sub
     if has_adj and not args.no_served:
         print(f"[bench] served leg: {args.requests} requests at {args.rate}/s", flush=True)
         line["served"] = served_leg(args.requests, args.rate, fill_cells=args.fill_cells)
