@@ -77,6 +77,12 @@ enum { LKS_OBJ_NONE = -1, LKS_OBJ_POWER = 0, LKS_OBJ_DRAG = 1, LKS_OBJ_TORQUE = 
 #define LKS_NORM_TIME 1 /* divide J by (n1 - n0 + 1)  */
 #define LKS_NORM_MASK 2 /* divide J by the mask count */
 enum { LKS_F32 = 0, LKS_F64 = 1 };
+/* Reverse sweep.  EXACT: the exact derivative of the discrete objective (the transposes of every
+ * forward step).  PAPER: the paper's own adjoint form (Sec. 2.4, Eqs. arho_ex, au_ex, as_ex and
+ * the sensitivity on D): the Brinkman source divides only the pulled moment 3 u~ by (1 + kappa),
+ * and the kappa seed is -(3 u~ / (1 + kappa)) . (u - u_S); an approximation of the gradient that
+ * approaches it as dx -> 0 (2D only; three plain launches per step, for verification). */
+enum { LKS_ADJ_EXACT = 0, LKS_ADJ_PAPER = 1 };
 #define LKS_STATE_FINAL (-1)
 
 /* ---- descriptor ------------------------------------------------------------------------- */
@@ -131,6 +137,8 @@ typedef struct {
     int io_on_device;            /* gamma, dJdgamma and read_state buffers are device pointers */
     void *stream;                /* hipStream_t, or NULL for the null stream */
     size_t hbm_budget_bytes;     /* 0 = no budget; else lks_create fails with LKS_ENOMEM above it */
+    int adjoint_form;            /* LKS_ADJ_EXACT (0) or LKS_ADJ_PAPER; PAPER needs dim 2 and is
+                                    not served by lks_begin (LKS_EUNSUPPORTED) */
 } lks_desc;
 
 typedef struct lks_ctx lks_ctx;

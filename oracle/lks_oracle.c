@@ -179,6 +179,7 @@ int or_validate(const or_desc *d) {
     }
     if (d->weight != OR_W_COS4 && d->weight != OR_W_LIN) return -13;
     if (d->interp != OR_INTERP_PAPER && d->interp != OR_INTERP_FLUID_ONE) return -14;
+    if (d->adj_form != OR_ADJ_EXACT && d->adj_form != OR_ADJ_PAPER) return -15;
     return 0;
 }
 
@@ -465,9 +466,28 @@ int or_step(const or_desc *d, const double *kappa, const double *uS, const doubl
 /* ------------------------------------------------------------------------------------------
  * Reverse of one forward step: the exact transpose of or_step, steps in reverse order.
  * ------------------------------------------------------------------------------------------ */
+static int step_T_core(const or_desc *d, const double *kappa, const double *uS, const double *u_prev,
+                       const double *u_cur, const double *P, const double *V, const double *U3,
+                       double *P_out, double *V_out, double *U3_out, double *kbar_out);
+
 int or_step_T(const or_desc *d, const double *kappa, const double *uS, const double *u_prev,
               const double *u_cur, const double *P, const double *V, double *P_out,
               double *V_out, double *kbar_out) {
+    return step_T_core(d, kappa, uS, u_prev, u_cur, P, V, NULL, P_out, V_out, NULL, kbar_out);
+}
+
+int or_step_T_paper(const or_desc *d, const double *kappa, const double *uS, const double *u_prev,
+                    const double *u_cur, const double *P, const double *V, const double *U3,
+                    double *P_out, double *V_out, double *U3_out, double *kbar_out) {
+    return step_T_core(d, kappa, uS, u_prev, u_cur, P, V, U3, P_out, V_out, U3_out, kbar_out);
+}
+
+/* U3 == NULL: the exact transpose.  Otherwise the paper's form of Sec. 2.4: U3 carries 3 u~ of
+ * the level being left (plus the objective's u-seed); only that part is divided by (1 + kappa)
+ * and only that part forms the kappa seed, and U3_out receives 3 u~ of the new level. */
+static int step_T_core(const or_desc *d, const double *kappa, const double *uS, const double *u_prev,
+                       const double *u_cur, const double *P, const double *V, const double *U3,
+                       double *P_out, double *V_out, double *U3_out, double *kbar_out) {
     grid_t g;
     lat_t L;
     make_grid(d, &g);
@@ -505,9 +525,17 @@ int or_step_T(const or_desc *d, const double *kappa, const double *uS, const dou
         Ps[idx] = lp[idx];
         double kb = 0.0;
         for (int a = 0; a < 3; ++a) {
-            double v = (a < D) ? lv[a * nc + idx] / (1.0 + k + ks) : 0.0;
+            double v = 0.0;
+            if (a < D && !U3) {
+                v = lv[a * nc + idx] / (1.0 + k + ks);
+                kb -= v * (u_cur[a * nc + idx] - uS[a * nc + idx]);
+            } else if (a < D) {
+                /* Eq. au_ex: u~ (1 + kappa) = u~* - seed; the rest of the adjoint velocity passes */
+                const double q = U3[a * nc + idx] / (1.0 + k + ks);
+                v = q + (lv[a * nc + idx] - U3[a * nc + idx]);
+                kb -= q * (u_cur[a * nc + idx] - uS[a * nc + idx]);
+            }
             Vs[a * nc + idx] = v;
-            if (a < D) kb -= v * (u_cur[a * nc + idx] - uS[a * nc + idx]);
         }
         kbar_out[idx] = kb;
     }
@@ -541,6 +569,7 @@ int or_step_T(const or_desc *d, const double *kappa, const double *uS, const dou
                 for (int b = 0; b < D; ++b) v += 9.0 * s[a][b] * u_prev[b * nc + idx];
             }
             V_out[a * nc + idx] = v;
+            if (U3_out) U3_out[a * nc + idx] = (a < D) ? 3.0 * ut[a] : 0.0;
             for (int b = 0; b < 3; ++b) st[(a * 3 + b) * nc + idx] = s[a][b];
         }
     }
@@ -738,7 +767,10 @@ int or_solve(const or_desc *d, const double *gamma, double *J, double *jn, doubl
         double *dV = (double *)malloc(sizeof(double) * 3 * nc);
         double *dK = (double *)malloc(sizeof(double) * nc);
         double *G = (double *)calloc(ndn, sizeof(double));
-        if (!P || !V || !P2 || !V2 || !kb || !dP || !dV || !dK || !G) {
+        const int paper = d->adj_form == OR_ADJ_PAPER;
+        double *U3 = paper ? (double *)calloc(3 * nc, sizeof(double)) : NULL;
+        double *U32 = paper ? (double *)malloc(sizeof(double) * 3 * nc) : NULL;
+        if (!P || !V || !P2 || !V2 || !kb || !dP || !dV || !dK || !G || (paper && (!U3 || !U32))) {
             rc = -102;
         } else {
             for (int n = N; n >= 1; --n) {
@@ -750,8 +782,15 @@ int or_solve(const or_desc *d, const double *gamma, double *J, double *jn, doubl
                     or_objective_partials(d, kappa, uS, r1, u1, dP, dV, dK);
                     for (long i = 0; i < nc; ++i) P[i] += sc * dP[i];
                     for (long i = 0; i < 3 * nc; ++i) V[i] += sc * dV[i];
+                    if (paper)  /* Eq. au_ex: the u-seed joins u~ before the division */
+                        for (long i = 0; i < 3 * nc; ++i) U3[i] += sc * dV[i];
                 }
-                or_step_T(d, kappa, uS, u0, u1, P, V, P2, V2, kb);
+                if (paper) {
+                    or_step_T_paper(d, kappa, uS, u0, u1, P, V, U3, P2, V2, U32, kb);
+                    memcpy(U3, U32, sizeof(double) * 3 * nc);
+                } else {
+                    or_step_T(d, kappa, uS, u0, u1, P, V, P2, V2, kb);
+                }
                 if (inwin)
                     for (long i = 0; i < nc; ++i) kb[i] += sc * dK[i];
                 or_transfer_T(d, n, kb, G);
@@ -761,6 +800,7 @@ int or_solve(const or_desc *d, const double *gamma, double *J, double *jn, doubl
             for (long i = 0; i < ndn; ++i) grad[i] = kpr[i] * G[i];
         }
         free(P); free(V); free(P2); free(V2); free(kb); free(dP); free(dV); free(dK); free(G);
+        free(U3); free(U32);
     }
 done:
     free(kref); free(kpr); free(kappa); free(uS); free(rho_t); free(u_t);

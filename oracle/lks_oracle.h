@@ -46,6 +46,7 @@ enum { OR_BC_PERIODIC = 0, OR_BC_VELOCITY = 1, OR_BC_PRESSURE = 2, OR_BC_ZERO_GR
        OR_BC_NOSLIP = 4 };
 enum { OR_OBJ_NONE = -1, OR_OBJ_POWER = 0, OR_OBJ_DRAG = 1, OR_OBJ_TORQUE = 2, OR_OBJ_J1 = 3,
        OR_OBJ_J2 = 4, OR_OBJ_MASS = 5 };
+enum { OR_ADJ_EXACT = 0, OR_ADJ_PAPER = 1 };
 #define OR_NORM_TIME 1
 #define OR_NORM_MASK 2
 
@@ -72,6 +73,7 @@ typedef struct {
     int obj_kind, obj_n0, obj_n1, obj_norm;
     double obj_centre[3], obj_dir[3];
     const unsigned char *obj_mask; /* [ncell] or NULL (= every node) */
+    int adj_form;            /* OR_ADJ_EXACT or OR_ADJ_PAPER (see or_step_T_paper) */
 } or_desc;
 
 /* 0 on success, negative on a malformed description. */
@@ -99,6 +101,17 @@ int or_apply_bc(const or_desc *d, double *rho, double *u);
 int or_step_T(const or_desc *d, const double *kappa, const double *uS, const double *u_prev,
               const double *u_cur, const double *P, const double *V, double *P_out,
               double *V_out, double *kbar_out);
+
+/* The paper's own (continuous-then-discretised) adjoint step, Sec. 2.4 Eqs. arho_ex, au_ex,
+ * as_ex: the same as or_step_T except that (i) the Brinkman source divides only the pulled
+ * velocity moment 3 u~ (carried in U3, with the objective's u-seed) by (1 + kappa), not the whole
+ * adjoint velocity, and (ii) the kappa seed is -(3 u~ / (1 + kappa)) . (u - u_S), from the pulled
+ * moment alone.  U3 [3*ncell] in, U3_out [3*ncell] = 3 u~ of the new level.  PARITY UNPINNED: it
+ * is not the derivative of any discrete map; the CPU tests check only that it reduces to the exact
+ * step where (i) and (ii) vanish and that its gradient approaches central differences. */
+int or_step_T_paper(const or_desc *d, const double *kappa, const double *uS, const double *u_prev,
+                    const double *u_cur, const double *P, const double *V, const double *U3,
+                    double *P_out, double *V_out, double *U3_out, double *kbar_out);
 
 /* Objective density summed over the mask at one step (un-normalised), and its partials
  * (overwritten; any pointer may be NULL). */

@@ -23,6 +23,7 @@ _INTERP = {"PAPER": 0, "FLUID_ONE": 1}
 _WEIGHT = {"COS4": 0, "LIN": 1}
 _BC = {"PERIODIC": 0, "VELOCITY": 1, "PRESSURE": 2, "ZERO_GRADIENT": 3, "NOSLIP": 4}
 _OBJ = {"NONE": -1, "POWER": 0, "DRAG": 1, "TORQUE": 2, "J1": 3, "J2": 4, "MASS": 5}
+_ADJ = {"EXACT": 0, "PAPER": 1}
 
 _dp = C.POINTER(C.c_double)
 _u8p = C.POINTER(C.c_uint8)
@@ -38,6 +39,7 @@ class OrDesc(C.Structure):
         ("kappa_static", _dp), ("g", C.c_double * 3), ("nsteps", C.c_int), ("motion", _dp),
         ("obj_kind", C.c_int), ("obj_n0", C.c_int), ("obj_n1", C.c_int), ("obj_norm", C.c_int),
         ("obj_centre", C.c_double * 3), ("obj_dir", C.c_double * 3), ("obj_mask", _u8p),
+        ("adj_form", C.c_int),
     ]
 
 
@@ -69,6 +71,7 @@ def lib():
         L.or_step.argtypes = [P, _dp, _dp, _dp, _dp, _dp, _dp]
         L.or_apply_bc.argtypes = [P, _dp, _dp]
         L.or_step_T.argtypes = [P, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.or_step_T_paper.argtypes = [P, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
         L.or_objective_step.argtypes = [P, _dp, _dp, _dp, _dp]
         L.or_objective_step.restype = C.c_double
         L.or_objective_partials.argtypes = [P, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
@@ -140,6 +143,7 @@ class Desc:
             assert m.size == self.nc
             self._keep.append(m)
             d.obj_mask = m.ctypes.data_as(_u8p)
+        d.adj_form = _ADJ[cfg.get("adjoint", "EXACT")]
         self.d = d
 
     @property
@@ -210,6 +214,17 @@ def step_T(cfg: dict, kappa, uS, u_prev, u_cur, P, V):
     kb = np.empty(D.nc)
     lib().or_step_T(D.ref, *[_ptr(x) for x in a], _ptr(Po), _ptr(Vo), _ptr(kb))
     return Po, Vo, kb
+
+
+def step_T_paper(cfg: dict, kappa, uS, u_prev, u_cur, P, V, U3):
+    D = Desc(cfg)
+    a = [np.ascontiguousarray(x, dtype=np.float64) for x in (kappa, uS, u_prev, u_cur, P, V, U3)]
+    Po = np.empty(D.nc)
+    Vo = np.empty((3, D.nc))
+    U3o = np.empty((3, D.nc))
+    kb = np.empty(D.nc)
+    lib().or_step_T_paper(D.ref, *[_ptr(x) for x in a], _ptr(Po), _ptr(Vo), _ptr(U3o), _ptr(kb))
+    return Po, Vo, U3o, kb
 
 
 def objective_step(cfg: dict, kappa, uS, rho, u) -> float:

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblks.so")
-SOURCES = ["lks_api.hip", "lks_kernels2d.hip", "lks_kernels3d.hip", "lks_kernels_common.hip"]
+SOURCES = ["lks_api.hip", "lks_kernels2d.hip", "lks_kernels3d.hip", "lks_kernels_common.hip",
+           "lks_kernels2d_paper.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC,

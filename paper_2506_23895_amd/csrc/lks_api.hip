@@ -52,7 +52,7 @@ struct Layout {
     size_t bytes = 0;
     // byte sizes of each allocation
     size_t b_state = 0, b_ckpt = 0, b_traj = 0, b_box = 0, b_kbar = 0, b_adj = 0, b_design = 0,
-           b_aux = 0, b_final = 0, b_pv = 0, b_args = 0, b_xring = 0;
+           b_aux = 0, b_final = 0, b_pv = 0, b_args = 0, b_xring = 0, b_padj = 0;
     long long max_blocks = 0;
     int prow = 1;            // rows of the objective-partials ring (steps reduced per batch)
     int banks = 1;           // trajectory/box store banks: 2 lets a segment be recomputed while
@@ -87,6 +87,10 @@ int plan(const lks_desc *d, Layout &L, std::string *err) {
     if (d->nsteps < 1) return fail(err, LKS_EINVAL, "nsteps must be >= 1");
     if (!d->motion) return fail(err, LKS_EINVAL, "motion table is NULL");
     if (d->checkpoint_every < 0) return fail(err, LKS_EINVAL, "checkpoint_every must be >= 0");
+    if (d->adjoint_form != LKS_ADJ_EXACT && d->adjoint_form != LKS_ADJ_PAPER)
+        return fail(err, LKS_EINVAL, "unknown adjoint form");
+    if (d->adjoint_form == LKS_ADJ_PAPER && d->dim != 2)
+        return fail(err, LKS_EUNSUPPORTED, "the paper's adjoint form is built for 2D");
     if (!std::isfinite(d->rho0) || !finite3(d->u0) || !finite3(d->body_force) || !finite3(d->xi_G))
         return fail(err, LKS_EINVAL, "non-finite initial state, force or xi_G");
 
@@ -220,6 +224,8 @@ int plan(const lks_desc *d, Layout &L, std::string *err) {
     L.b_design = (size_t)L.nd * (3 * e + 2 * 8);  // gamma, kref, sens out; kprime, G
     L.max_blocks = lks::fwd_blocks(g, d->lattice, (int)L.esz);
     L.b_pv = (D == 3 && !L.fwd_only) ? (size_t)4 * L.F * e : 0;  // (P*, V*) between the 3D adjoint kernels
+    // the paper's adjoint form: (P*, V*), 3 u~ of two levels and s~ (xx, xy, yy)
+    L.b_padj = (d->adjoint_form == LKS_ADJ_PAPER && !L.fwd_only) ? (size_t)(nf + 2 * D + 3) * L.F * e : 0;
     // objective partials: a ring of rows of per-wave (2D) or per-block (3D) sums, one row per step,
     // reduced into j^n every kPartialRows steps of the window and at its end
     const long long obj_rows = d->objective.kind == LKS_OBJ_NONE ? 1 : (d->objective.n1 - d->objective.n0 + 1);
@@ -230,7 +236,7 @@ int plan(const lks_desc *d, Layout &L, std::string *err) {
     if (d->rho_init || d->u_init) L.b_aux += nf * L.F * e;
     L.b_args = (size_t)N * (L.esz == 8 ? lks::args_bytes<double>() : lks::args_bytes<float>()) + 4096;
     L.bytes = L.b_state + L.b_ckpt + L.b_traj + L.b_box + L.b_kbar + L.b_adj + L.b_final +
-              L.b_design + L.b_aux + L.b_pv + L.b_args + L.b_xring;
+              L.b_design + L.b_aux + L.b_pv + L.b_args + L.b_xring + L.b_padj;
     if (d->hbm_budget_bytes && L.bytes > d->hbm_budget_bytes)
         return fail(err, LKS_ENOMEM, "context needs " + std::to_string(L.bytes) +
                                           " bytes, over the HBM budget");
@@ -253,7 +259,7 @@ struct lks_ctx {
     // device memory
     char *state = nullptr, *ckpt = nullptr, *traj = nullptr, *box = nullptr, *kbar = nullptr,
          *adj = nullptr, *fin = nullptr, *gamma = nullptr, *kref = nullptr, *sens = nullptr,
-         *kstatic = nullptr, *init = nullptr, *pv = nullptr, *xring = nullptr;
+         *kstatic = nullptr, *init = nullptr, *pv = nullptr, *xring = nullptr, *padj = nullptr;
     double *kprime = nullptr, *G = nullptr, *jn = nullptr, *partials = nullptr;
     unsigned int *counter = nullptr;
     int *flag = nullptr;
@@ -813,6 +819,21 @@ lks::AdjArgs<T> make_adj_args(lks_ctx *c, int n, int j, int acur) {
     return a;
 }
 
+// the paper's adjoint form: (P*, V*) scratch, 3 u~ ping-pong (in slot acur, out slot 1 - acur), s~
+template <typename T>
+void set_paper_args(lks_ctx *c, lks::AdjArgs<T> &a, int acur) {
+    const int D = c->d.dim;
+    T *b = reinterpret_cast<T *>(c->padj);
+    const long long F = c->L.F;
+    a.Ps = b;
+    for (int k = 0; k < 3; ++k) {
+        a.Vs[k] = k < D ? b + (1 + k) * F : nullptr;
+        a.U3in[k] = k < D ? b + (1 + D + acur * D + k) * F : nullptr;
+        a.U3out[k] = k < D ? b + (1 + D + (1 - acur) * D + k) * F : nullptr;
+        a.st[k] = b + (1 + 3 * D + k) * F;
+    }
+}
+
 template <typename T>
 lks::SensArgs<T> make_sens_args(lks_ctx *c, int n) {
     lks::SensArgs<T> sa{};
@@ -840,6 +861,7 @@ int adjoint_impl(lks_ctx *c) {
     // argument blocks: recomputed steps (every segment but the last), one transfer-only block per
     // recomputed segment, then the adjoint steps and the gathers
     const int nrec = (S - 1) * K, nfa = nrec + (S - 1);
+    const bool paper = c->d.adjoint_form == LKS_ADJ_PAPER;
     auto *ra = reinterpret_cast<lks::FwdArgs<T> *>(c->arghost);
     auto *aa = reinterpret_cast<lks::AdjArgs<T> *>(c->arghost + (size_t)nfa * sizeof(lks::FwdArgs<T>));
     auto *sa = reinterpret_cast<lks::SensArgs<T> *>(reinterpret_cast<char *>(aa) + (size_t)N * sizeof(lks::AdjArgs<T>));
@@ -864,11 +886,12 @@ int adjoint_impl(lks_ctx *c) {
             }
             for (int n = n1; n >= n0; --n) {
                 aa[n - 1] = make_adj_args<T>(c, n, n - seg * K, acur);
+                if (paper) set_paper_args<T>(c, aa[n - 1], acur);
                 sa[n - 1] = make_sens_args<T>(c, n);
                 acur = 1 - acur;
             }
         }
-        if (D == 2) {  // each adjoint launch also runs the gather of the step after it (kappa_bar
+        if (D == 2 && !paper) {  // each adjoint launch also runs the gather of the step after it (kappa_bar
                        // of consecutive steps lives in alternate halves of the kappa_bar buffer)
             const auto *dsa_dev = reinterpret_cast<const lks::SensArgs<T> *>(
                 c->argdev + (size_t)nfa * sizeof(lks::FwdArgs<T>) + (size_t)N * sizeof(lks::AdjArgs<T>));
@@ -884,6 +907,8 @@ int adjoint_impl(lks_ctx *c) {
     const auto *daa = reinterpret_cast<const lks::AdjArgs<T> *>(c->argdev + (size_t)nfa * sizeof(lks::FwdArgs<T>));
     const auto *dsa = reinterpret_cast<const lks::SensArgs<T> *>(reinterpret_cast<const char *>(daa) + (size_t)N * sizeof(lks::AdjArgs<T>));
     HIPCHK(c, lks::launch_fill<T>(ad.r, T(0), (long long)(1 + D) * L.F, c->stream));
+    if (paper)  // 3 u~ of level N starts at zero like lambda^N
+        HIPCHK(c, lks::launch_fill<T>(reinterpret_cast<T *>(c->padj), T(0), (long long)(1 + 3 * D) * L.F, c->stream));
     HIPCHK(c, lks::launch_fill<double>(c->G, 0.0, L.nd, c->stream));
     if ((rc = reset_flags(c, false, c->stream))) return rc;
     hipStream_t sr = c->stream2 ? c->stream2 : c->stream;  // recompute stream
@@ -912,15 +937,24 @@ int adjoint_impl(lks_ctx *c) {
         }
         c->overlap = seg >= 1 && sr != c->stream;
         for (int n = n1; n >= n0; --n) {
-            if (D == 2) rc = launch_adj_fused<T>(c, daa + (n - 1), aa[n - 1]);
-            else rc = launch_adj_dev<T>(c, daa + (n - 1), dsa + (n - 1));
+            if (paper) {
+                {
+                    Timed t(c, 1, c->stream);
+                    HIPCHK(c, lks::launch_padj2d<T>(daa + (n - 1), L.g, c->stream));
+                }
+                rc = launch_sens_dev<T>(c, dsa + (n - 1));
+            } else if (D == 2) {
+                rc = launch_adj_fused<T>(c, daa + (n - 1), aa[n - 1]);
+            } else {
+                rc = launch_adj_dev<T>(c, daa + (n - 1), dsa + (n - 1));
+            }
             if (rc) return rc;
             if (scan_adj_step(n) && (rc = scan_adj<T>(c, aa[n - 1], n, c->stream))) return rc;
         }
         c->overlap = false;
         if (sr != c->stream) HIPCHK(c, hipEventRecord(c->ev_adj, c->stream));
     }
-    if (D == 2 && (rc = launch_sens_dev<T>(c, dsa))) return rc;  // gather of step 1
+    if (D == 2 && !paper && (rc = launch_sens_dev<T>(c, dsa))) return rc;  // gather of step 1
     HIPCHK(c, lks::launch_scan<double>(c->G, L.nd, nullptr, 0, 1, c->flag + 2, 1, c->stream));
     int flag[3] = {INT_MAX, 0, 0};
     HIPCHK(c, hipMemcpyAsync(flag + 1, c->flag + 1, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -969,6 +1003,7 @@ int create_impl(const lks_desc *d, lks_ctx *c) {
     ALLOC(adj, L.b_adj)
     ALLOC(fin, L.b_final)
     ALLOC(pv, L.b_pv)
+    ALLOC(padj, L.b_padj)
     ALLOC(argdev, L.b_args)
     c->argcap = L.b_args - 256;  // the last 256 bytes hold tile0
     if (hipHostMalloc(reinterpret_cast<void **>(&c->arghost), L.b_args, 0) != hipSuccess) {
@@ -995,9 +1030,10 @@ int create_impl(const lks_desc *d, lks_ctx *c) {
     HIPCHK(c, hipMemset(c->counter, 0, 64));
     HIPCHK(c, hipMemset(c->tile0, 0, 256));
     // padded row tails are never written by the kernels: start every field buffer at zero
-    for (char *b : {c->state, c->ckpt, c->traj, c->adj, c->fin})
+    for (char *b : {c->state, c->ckpt, c->traj, c->adj, c->fin, c->padj})
         if (b) HIPCHK(c, hipMemset(b, 0, b == c->state ? L.b_state : b == c->ckpt ? L.b_ckpt
-                                         : b == c->traj ? L.b_traj : b == c->adj ? L.b_adj : L.b_final));
+                                         : b == c->traj ? L.b_traj : b == c->adj ? L.b_adj
+                                         : b == c->padj ? L.b_padj : L.b_final));
     if (d->kappa_static) {
         ALLOC(kstatic, L.F * e)
         rc = e == 8 ? upload_padded<double>(c, c->kstatic, d->kappa_static, 1)
@@ -1800,6 +1836,8 @@ void lks_batch_destroy(lks_batch *b) {
 }
 
 int lks_begin(lks_ctx *c, const void *gamma, void *dJdgamma) {
+    if (c && c->d.adjoint_form != LKS_ADJ_EXACT)
+        return set_err(c, LKS_EUNSUPPORTED, "the served path runs the exact adjoint only");
     if (!c) return LKS_EINVAL;
     if (!gamma || !dJdgamma) return set_err(c, LKS_EINVAL, "gamma and dJdgamma are required");
     if (!c->d.io_on_device) return set_err(c, LKS_EINVAL, "lks_begin needs an io_on_device context");

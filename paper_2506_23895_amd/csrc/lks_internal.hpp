@@ -110,6 +110,11 @@ struct AdjArgs {
     T *Vs[3];
     const SensArgs<T> *sens;  // 2D: gather of the previous adjoint step run by extra blocks, or null
     long long sens_blocks;
+    // the paper's adjoint form (2D): 3 u~ of the level being left and of the new one, and the
+    // s~ fields (xx, xy, yy) between the moment and strain launches; Ps / Vs hold (P*, V*)
+    const T *U3in[3];
+    T *U3out[3];
+    T *st[3];
 };
 
 template <typename T>
@@ -181,6 +186,9 @@ template <typename T>
 hipError_t launch_adj3d_batch(const AdjArgs<T> *args, const long long *blk0, long long nblk,
                               const long long *tile0, long long ntiles, int njobs, int lattice, bool pz,
                               hipStream_t s);
+// the paper's adjoint step in 2D: three launches (prep, moments, strain) of one job
+template <typename T>
+hipError_t launch_padj2d(const AdjArgs<T> *args, const Geom &g, hipStream_t s);
 template <typename T>
 hipError_t launch_sens_batch(const SensArgs<T> *args, const long long *blk0, int njobs, long long nblk,
                              hipStream_t s);

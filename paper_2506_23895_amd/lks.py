@@ -29,6 +29,7 @@ _WEIGHT = {"COS4": 0, "LIN": 1}
 _BC = {"PERIODIC": 0, "VELOCITY": 1, "PRESSURE": 2, "ZERO_GRADIENT": 3, "NOSLIP": 4}
 _OBJ = {"NONE": -1, "POWER": 0, "DRAG": 1, "TORQUE": 2, "J1": 3, "J2": 4, "MASS": 5}
 _PREC = {"F32": 0, "F64": 1}
+_ADJ = {"EXACT": 0, "PAPER": 1}
 
 EXPORTS = ["lks_query_bytes", "lks_create", "lks_destroy", "lks_forward", "lks_adjoint",
            "lks_sensitivity", "lks_read_state", "lks_read_objective_steps", "lks_set_timing",
@@ -62,6 +63,7 @@ class LksDesc(C.Structure):
         ("body_force", C.c_double * 3), ("nsteps", C.c_int), ("motion", C.POINTER(LksMotion)),
         ("objective", LksObjective), ("precision", C.c_int), ("checkpoint_every", C.c_int),
         ("io_on_device", C.c_int), ("stream", C.c_void_p), ("hbm_budget_bytes", C.c_size_t),
+        ("adjoint_form", C.c_int),
     ]
 
 
@@ -178,6 +180,7 @@ class _DescHolder:
         d.io_on_device = 1 if io_on_device else 0
         d.stream = stream
         d.hbm_budget_bytes = int(hbm_budget)
+        d.adjoint_form = _ADJ[cfg.get("adjoint", "EXACT")]
         self.d = d
 
 

@@ -16,7 +16,8 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 CSRC = os.path.join(ROOT, "paper_2506_23895_amd", "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "liblks_emu.so")
-SOURCES = ["lks_api.hip", "lks_kernels2d.hip", "lks_kernels3d.hip", "lks_kernels_common.hip"]
+SOURCES = ["lks_api.hip", "lks_kernels2d.hip", "lks_kernels3d.hip", "lks_kernels_common.hip",
+           "lks_kernels2d_paper.hip"]
 FLAGS = ["-std=c++20", "-O1", "-g", "-fPIC", "-fno-omit-frame-pointer", "-fsanitize=address",
          "-Wno-attributes", "-Wno-ignored-attributes", "-I", HERE, "-I", os.path.join(ROOT, "include"),
          "-I", CSRC]

@@ -33,6 +33,9 @@ CASES = {
     # 2D: wave strips with x faces, footprint marches, fused gather
     "d2q9_small": {"module": "test_gpu_parity_2d", "builder": "small", "kwargs": {"N": 10, "K": 4},
                    "seed": 3, "ckpt": True},
+    # the paper's adjoint form (its three plain launches), pressure outlet
+    "d2q9_paper_adjoint": {"module": "test_gpu_parity_2d", "builder": "small", "case": "pressure_outlet",
+                           "kwargs": {"N": 12, "K": 5}, "seed": 3, "override": {"adjoint": "PAPER"}},
 }
 
 FULL = os.environ.get("LKS_EMU_FULL") == "1"
@@ -76,6 +79,7 @@ def test_emulated_kernels_in_bounds_and_match_oracle(emu_lib, name, tmp_path):
     sys.path.insert(0, os.path.join(EMU))
     from run_case import build_cfg
     cfg = build_cfg(spec)
+    cfg.update(spec.get("override", {}))
     g = I.gamma_field(cfg["nd"], cfg["dim"], spec["seed"])
     want_grad = cfg["objective"]["kind"] != "NONE"
     o = run_oracle(cfg, g, grad=want_grad, traj=bool(spec.get("ckpt")))

@@ -122,6 +122,16 @@ def test_c4_copy48_fp32():
     print(compare(cfg, g, **F32))
 
 
+def test_c4_full_horizon_copy32_fp32():
+    """C4's lattice parameters (D3Q19, x inflow / outflow, periodic y and z, rotation about z at
+    2 pi / 1500, nu = 0.0192, TORQUE) on a 32^3 copy with a 12^3 design over C4's whole horizon:
+    3000 steps with a checkpoint every 50 (60 segments recomputed)."""
+    cfg = I.config_c4(n_side=32, nd_side=12, precision="F32", nsteps=3000, checkpoint_every=50)
+    announce("c4 copy 32 fp32, 3000 steps")
+    g = I.gamma_field(cfg["nd"], 3, 3)
+    print(compare(cfg, g, **F32))
+
+
 @pytest.mark.parametrize("nz", [64, 128])
 def test_c4_slab_chunks_fp32(nz):
     """C4's lattice parameters on a 256 x 256 x nz slab for 3 steps with a checkpoint every 2 (so
