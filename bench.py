@@ -449,6 +449,7 @@ def main() -> int:
     ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--requests", type=int, default=12, help="served leg: number of requests")
     ap.add_argument("--rate", type=float, default=50.0, help="served leg: arrivals per second")
+    ap.add_argument("--rates", default="", help="c5: comma-separated arrival rates to sweep")
     ap.add_argument("--no-served", action="store_true", help="skip the served leg")
     ap.add_argument("--no-extra", action="store_true", help="skip the c4 and c2 legs of the default line")
     ap.add_argument("--fill-cells", type=float, default=0.0,
@@ -508,6 +509,30 @@ def main() -> int:
         print(f"[bench] calibration copy of {a.numel() * 4} bytes done", flush=True)
         del a, b
 
+    if args.workload == "c5" and args.rates:
+        # rate sweep: the same seeded request list shape at each rate, served then plain
+        rows, sweep = [], []
+        for rate in [float(v) for v in args.rates.split(",")]:
+            print(f"[bench] served sweep: {args.requests} requests at {rate}/s", flush=True)
+            sv = served_leg(args.requests, rate, fill_cells=args.fill_cells)
+            sweep.append(sv)
+            a, b = sv["served"], sv["plain"]
+            rows.append(f"{rate:6.1f} {a.get('evals_per_s', 0):8.3f} {a.get('p50_latency_s', 0):7.2f} "
+                        f"{a.get('p99_latency_s', 0):7.2f} {b.get('evals_per_s', 0):8.3f} "
+                        f"{b.get('p50_latency_s', 0):7.2f} {b.get('p99_latency_s', 0):7.2f} "
+                        f"{sv.get('speedup_vs_plain', 0):6.3f}")
+        print("# rate  served: evals/s  p50 s  p99 s | plain: evals/s  p50 s  p99 s | served/plain")
+        print("\n".join(rows), flush=True)
+        best = max(sweep, key=lambda v: v["served"].get("evals_per_s", 0))
+        print(json.dumps({
+            "metric": "sens-evals/s served (continuous batching) + p50/p99 latency",
+            "value": best["served"].get("evals_per_s"), "unit": "evals/s", "n_gpus": 1, "steps": 1,
+            "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "c5_served_mix", "requests": args.requests, "rates": args.rates,
+                       "fill_cells": args.fill_cells, "parallelism": "single GPU"},
+            "sweep": sweep}), flush=True)
+        return 0
     if args.workload == "c5":
         t0 = time.perf_counter()
         sv = served_leg(args.requests, args.rate, fill_cells=args.fill_cells)

@@ -237,7 +237,9 @@ def config_c4(n_side: int = 256, nd_side: int = 96, precision: str = "F32", nste
 
 def served_job(rng: np.random.Generator, precision: str = "F32") -> dict:
     """One request of the served mix: 2D 128^2..1024^2 or 3D 64^3..160^3, design at 40%,
-    500..5000 steps, checkpoints every ceil(sqrt(steps)) steps."""
+    500..5000 steps, checkpoints every ceil(sqrt(steps)) steps.  Rotation at a tip speed of 0.1, or
+    heave of amplitude 0.1 n at a peak speed of 0.1 (at a fixed period of 2000 steps the peak heave
+    speed of the largest 2D grids reaches 0.32, and those jobs go non-finite)."""
     is3d = bool(rng.integers(0, 2))
     rotate = bool(rng.integers(0, 2))
     nsteps = int(rng.integers(500, 5001))
@@ -255,7 +257,7 @@ def served_job(rng: np.random.Generator, precision: str = "F32") -> dict:
         mot = motion_rotation(nsteps, centre, 0.1 / tip)
         obj = objective("POWER", 1, nsteps)
     else:
-        mot = motion_heave(nsteps, centre, 0.1 * s, 2 * math.pi / 2000)
+        mot = motion_heave(nsteps, centre, 0.1 * s, 0.1 / (0.1 * s))
         obj = objective("DRAG", 1, nsteps, norm=1)
     bcs = channel_bcs(dim, U_IN, walls=(dim == 2))
     if dim == 3:

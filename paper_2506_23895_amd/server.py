@@ -10,15 +10,23 @@ kernels of all jobs share one launch per kernel kind, so requests that arrive wh
 overlap with them on the device.  Finished jobs are detected with lks_poll (non-blocking), their
 memory is released and queued requests are admitted.
 
+Two ways in: serve(requests) replays a list of requests with arrival times (the benchmark);
+submit(cfg, gamma) hands one request to a serving thread and returns a concurrent.futures.Future
+that resolves to (J, dJ/dgamma, latency in s), or raises if the job failed (non-finite state, over
+the HBM budget).
+
 serve_plain() runs the same request list back to back through lks_forward / lks_adjoint /
 lks_sensitivity, one job at a time: the baseline the batched path is compared with.
 """
 from __future__ import annotations
 
+import concurrent.futures as cf
 import math
+import queue
+import threading
 import time
 from dataclasses import dataclass, field
-from typing import List, Optional
+from typing import List, Optional, Sequence
 
 import numpy as np
 import torch
@@ -66,6 +74,8 @@ class _Active:
     admitted: float
     done: bool = False
     rounds: int = 0         # micro-steps taken (a job needs about 2 N: forward, then reverse)
+    waited: int = 0         # rounds since this job last took a micro-step
+    future: Optional[cf.Future] = None
 
     @property
     def cells(self) -> int:
@@ -77,69 +87,164 @@ class _Active:
         return self.cells * max(1, 2 * self.req.cfg["nsteps"] - self.rounds)
 
 
+def select_round(jobs: Sequence, fill_cells: float, max_wait: int) -> list:
+    """The jobs that take a micro-step this round.  fill_cells <= 0: every job.  Otherwise first
+    every job that has waited max_wait rounds or more (so no job is passed over for ever, however
+    long it is), then the jobs with the least remaining work (cells x micro-steps left), until the
+    round holds fill_cells cells: short jobs finish first."""
+    if fill_cells <= 0 or not jobs:
+        return list(jobs)
+    due = [a for a in jobs if a.waited >= max_wait]
+    rest = sorted((a for a in jobs if a.waited < max_wait), key=lambda a: a.remaining)
+    order = sorted(due, key=lambda a: -a.waited) + rest
+    acc, k = 0, 0
+    while k < len(order) and (k == 0 or acc < fill_cells or order[k].waited >= max_wait):
+        acc += order[k].cells
+        k += 1
+    return order[:k]
+
+
 class Server:
     """fill_cells > 0: each round advances only the admitted jobs with the least remaining work
-    (cells x micro-steps left), as many as it takes to reach fill_cells cells in the round, so
-    that short jobs finish first instead of sharing every round with long ones; 0 advances every
-    admitted job every round."""
+    (cells x micro-steps left), as many as it takes to reach fill_cells cells in the round, so that
+    short jobs finish first instead of sharing every round with long ones, and every job at least
+    once every max_wait rounds; 0 advances every admitted job every round."""
 
-    def __init__(self, hbm_budget: int = 0, max_active: int = 32, fill_cells: float = 0.0):
+    def __init__(self, hbm_budget: int = 0, max_active: int = 32, fill_cells: float = 0.0,
+                 max_wait: int = 64):
         free, total = torch.cuda.mem_get_info()
         self.budget = int(hbm_budget) if hbm_budget else int(0.8 * free)
         self.max_active = max_active
         self.fill_cells = float(fill_cells)
+        self.max_wait = int(max_wait)
+        self.device = torch.cuda.current_device()
         self.stream = torch.cuda.current_stream().cuda_stream
         self.batch = lks.Batch(self.stream)
         self.rounds = 0
         self.admission_waits = 0
         self.peak_used = 0
+        self._inbox: "queue.Queue" = queue.Queue()
+        self._thread: Optional[threading.Thread] = None
+        self._stop = threading.Event()
+        self._t0 = time.perf_counter()
+        self._next_id = 0
+        self._lock = threading.Lock()
+
+    # -- request interface: a serving thread and futures ----------------------------------------
+    def submit(self, cfg: dict, gamma) -> cf.Future:
+        """Queue one sensitivity evaluation; the Future resolves to (J, dJ/dgamma, latency s)."""
+        fut: cf.Future = cf.Future()
+        with self._lock:
+            rid = self._next_id
+            self._next_id += 1
+            if self._thread is None:
+                self._thread = threading.Thread(target=self._run, name="lks-server", daemon=True)
+                self._thread.start()
+        req = Request(rid, time.perf_counter() - self._t0, cfg, np.asarray(gamma))
+        self._inbox.put((req, fut))
+        return fut
+
+    def _run(self):
+        torch.cuda.set_device(self.device)
+        with torch.cuda.stream(torch.cuda.ExternalStream(self.stream)):
+            self._loop(live=True)
+
+    def shutdown(self, wait: bool = True):
+        """Stop the serving thread once every submitted request is done (wait) or now."""
+        if self._thread is not None:
+            self._stop.set()
+            if wait:
+                self._thread.join()
+            self._thread = None
 
     def serve(self, requests: List[Request]) -> List[Result]:
-        pending = sorted(requests, key=lambda r: r.arrival)
+        """Replay requests at their arrival times (seconds after the call); results by request id."""
+        self._t0 = time.perf_counter()
+        for rq in sorted(requests, key=lambda r: r.arrival):
+            self._inbox.put((rq, None))
+        return sorted(self._loop(live=False, expected=len(requests)), key=lambda r: r.rid)
+
+    def _loop(self, live: bool, expected: int = 0) -> List[Result]:
+        pending: List[tuple] = []
         active: List[_Active] = []
         used = 0
         results: List[Result] = []
-        t0 = time.perf_counter()
+        t0 = self._t0
         dev = torch.device("cuda")
-        while pending or active:
+
+        def finish(res: Result, fut: Optional[cf.Future], grad=None):
+            results.append(res)
+            if fut is not None:
+                if res.status == "ok":
+                    fut.set_result((res.J, grad if grad is not None else res.grad, res.latency))
+                else:
+                    code = (lks.LKS_ENONFINITE if "non-finite" in res.status else
+                            lks.LKS_ENOMEM if "budget" in res.status else lks.LKS_EINVAL)
+                    fut.set_exception(lks.LksError(code, res.status))
+
+        while True:
+            while True:  # take what has been handed in
+                try:
+                    pending.append(self._inbox.get_nowait())
+                except queue.Empty:
+                    break
+            pending.sort(key=lambda p: p[0].arrival)
+            if not live and not pending and not active and len(results) >= expected:
+                break
+            if live and not pending and not active:
+                if self._stop.is_set() and self._inbox.empty():
+                    break
+                try:
+                    pending.append(self._inbox.get(timeout=0.005))
+                except queue.Empty:
+                    pass
+                continue
             now = time.perf_counter() - t0
             # admission: FIFO, by HBM ledger and slot count
-            while pending and pending[0].arrival <= now and len(active) < self.max_active:
-                rq = pending[0]
-                need = lks.query_bytes(rq.cfg)
+            while pending and pending[0][0].arrival <= now and len(active) < self.max_active:
+                rq, fut = pending[0]
+                try:
+                    need = lks.query_bytes(rq.cfg)
+                except lks.LksError as e:
+                    pending.pop(0)
+                    finish(Result(rq.rid, float("nan"), np.empty(0), rq.arrival, now, now,
+                                  f"failed: {e}"), fut)
+                    continue
                 if need > self.budget:
                     pending.pop(0)
-                    results.append(Result(rq.rid, float("nan"), np.empty(0), rq.arrival, now, now,
-                                          "rejected: over the HBM budget"))
+                    finish(Result(rq.rid, float("nan"), np.empty(0), rq.arrival, now, now,
+                                  "rejected: over the HBM budget"), fut)
                     continue
                 if used + need > self.budget:
                     self.admission_waits += 1
                     break
                 pending.pop(0)
                 dt = torch.float64 if rq.cfg["precision"] == "F64" else torch.float32
-                s = lks.Solver(rq.cfg, io_on_device=True, stream=self.stream)
-                g = torch.as_tensor(rq.gamma, dtype=dt).to(dev)
-                out = torch.empty_like(g)
-                s.begin(g, out)
+                try:
+                    s = lks.Solver(rq.cfg, io_on_device=True, stream=self.stream)
+                    g = torch.as_tensor(rq.gamma, dtype=dt).to(dev)
+                    out = torch.empty_like(g)
+                    s.begin(g, out)
+                except lks.LksError as e:
+                    finish(Result(rq.rid, float("nan"), np.empty(0), rq.arrival, now, now,
+                                  f"failed: {e}"), fut)
+                    continue
                 used += need
                 self.peak_used = max(self.peak_used, used)
-                active.append(_Active(rq, s, g, out, need, time.perf_counter() - t0))
+                active.append(_Active(rq, s, g, out, need, time.perf_counter() - t0, future=fut))
             if not active:
                 if pending:
-                    time.sleep(max(0.0, min(0.01, pending[0].arrival - (time.perf_counter() - t0))))
+                    time.sleep(max(0.0, min(0.01, pending[0][0].arrival - (time.perf_counter() - t0))))
                 continue
             running = [a for a in active if not a.done]
-            if running and self.fill_cells > 0:
-                running.sort(key=lambda a: a.remaining)
-                acc, k = 0, 0
-                while k < len(running) and (k == 0 or acc < self.fill_cells):
-                    acc += running[k].cells
-                    k += 1
-                running = running[:k]
-            if running:
-                flags = self.batch.round([a.solver for a in running])
+            chosen = select_round(running, self.fill_cells, self.max_wait)
+            if chosen:
+                flags = self.batch.round([a.solver for a in chosen])
                 self.rounds += 1
-                for a, f in zip(running, flags):
+                picked = set(id(a) for a in chosen)
+                for a in running:
+                    a.waited = 0 if id(a) in picked else a.waited + 1
+                for a, f in zip(chosen, flags):
                     a.done = bool(f)
                     a.rounds += 1
             # retire completed jobs without waiting on the stream
@@ -152,17 +257,18 @@ class Server:
                         J, status = float("nan"), f"failed: {e}"
                     fin = time.perf_counter() - t0
                     cfg = a.req.cfg
-                    results.append(Result(a.req.rid, J, a.out.cpu().numpy(), a.req.arrival,
-                                          a.admitted, fin, status,
-                                          float(np.prod(cfg["n"])) * cfg["nsteps"], alg_bytes(cfg)))
+                    grad = a.out.cpu().numpy()
+                    finish(Result(a.req.rid, J, grad, a.req.arrival, a.admitted, fin, status,
+                                  float(np.prod(cfg["n"])) * cfg["nsteps"], alg_bytes(cfg)), a.future)
                     a.solver.close()
                     used -= a.nbytes
                     active.remove(a)
             if active and all(a.done for a in active):
                 time.sleep(0.0005)  # everything enqueued: wait for the device
-        return sorted(results, key=lambda r: r.rid)
+        return results
 
     def close(self):
+        self.shutdown(wait=True)
         self.batch.close()
 
 

@@ -114,3 +114,34 @@ def test_server_shortest_work_first_bitwise():
         assert a.status == b.status == "ok"
         assert a.J == b.J, (a.rid, a.J, b.J)
         assert np.array_equal(a.grad, b.grad), a.rid
+
+
+def test_submit_returns_futures_with_the_plain_results():
+    """Server.submit: requests handed in while others run resolve to (J, dJ/dgamma, latency),
+    bitwise those of the single-job entry points; a job whose state goes non-finite raises."""
+    import torch
+    from paper_2506_23895_amd import lks
+    from paper_2506_23895_amd.server import Server
+    torch.cuda.set_device(0)
+    cfgs = jobs()[:3]
+    gammas = [I.gamma_field(c["nd"], c["dim"], 30 + k).astype(np.float32) for k, c in enumerate(cfgs)]
+    bad = dict(cfgs[1], nu=0.6)  # unstable viscosity: the forward goes non-finite
+    announce("served: submit and futures")
+    srv = Server()
+    futs = []
+    for k, (c, g) in enumerate(zip(cfgs, gammas)):
+        futs.append(srv.submit(c, g))
+        if k == 0:
+            fbad = srv.submit(bad, gammas[1])
+    results = [f.result(timeout=300) for f in futs]
+    with pytest.raises(lks.LksError) as ei:
+        fbad.result(timeout=300)
+    assert ei.value.code == lks.LKS_ENONFINITE
+    srv.close()
+    for k, c in enumerate(cfgs):
+        with lks.Solver(c) as s:
+            Jp = s.forward(gammas[k])
+            s.adjoint()
+            gp = s.sensitivity()
+        J, grad, lat = results[k]
+        assert J == Jp and np.array_equal(grad, gp) and lat > 0, k

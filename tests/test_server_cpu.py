@@ -1,0 +1,57 @@
+"""Host logic of the served path: which jobs take a micro-step in a round (shortest remaining work
+first, aged by waiting), without a GPU."""
+from dataclasses import dataclass
+
+from paper_2506_23895_amd.server import select_round
+
+
+@dataclass
+class Job:
+    cells: int
+    left: int          # micro-steps left
+    waited: int = 0
+
+    @property
+    def remaining(self):
+        return self.cells * self.left
+
+
+def simulate(max_wait, rounds=400):
+    """One long job among short ones that keep arriving; returns the rounds the long job waited
+    at most between two of its micro-steps."""
+    long_job = Job(cells=1_000_000, left=10_000)
+    shorts = [Job(cells=100_000, left=50) for _ in range(4)]
+    worst = 0
+    for r in range(rounds):
+        jobs = [long_job] + shorts
+        chosen = select_round(jobs, fill_cells=300_000, max_wait=max_wait)
+        ids = set(id(j) for j in chosen)
+        for j in jobs:
+            if id(j) in ids:
+                j.waited = 0
+                j.left -= 1
+            else:
+                j.waited += 1
+        worst = max(worst, long_job.waited)
+        shorts = [j for j in shorts if j.left > 0]
+        while len(shorts) < 4:  # sustained arrivals of short jobs
+            shorts.append(Job(cells=100_000, left=50))
+    return worst
+
+
+def test_every_job_each_round_without_fill():
+    jobs = [Job(10, 5), Job(20, 1)]
+    assert select_round(jobs, 0.0, 64) == jobs
+
+
+def test_shortest_work_first_fills_the_round():
+    a, b, c = Job(100, 10), Job(100, 2), Job(300, 1)
+    # keys (cells x steps left) b 200, c 300, a 1000: b alone holds 100 cells < 150, so c joins
+    assert select_round([a, b, c], 150, 64) == [b, c]
+    a.waited = 64  # a job that has waited max_wait rounds goes first, whatever its key
+    assert select_round([a, b, c], 150, 64)[0] is a
+
+
+def test_long_job_is_not_starved():
+    assert simulate(max_wait=10**9) >= 399     # shortest-first alone: never picked
+    assert simulate(max_wait=64) == 64         # picked again after at most max_wait rounds
