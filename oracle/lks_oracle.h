@@ -23,11 +23,15 @@
  * continuous-then-discretised adjoint); the readings of silent or garbled passages are listed
  * in the design notes of the repository.
  *
- * Pins: every function here is checked in the CPU test suite against closed forms (shear-wave
- * decay, Poiseuille, Couette), invariants (mass conservation, uniform flow, rigid isometry),
- * special cases (integer-shift transfer, quarter-turn permutation), transpose identities and
- * central finite differences of J.  The Taylor-Couette comparison of the paper's Appendix is a
- * physics check within the penalisation error.
+ * Pins: every function here except or_step_T_paper is checked in the CPU test suite against
+ * closed forms (shear-wave decay, Poiseuille, Couette, the pressure-driven channel, objective
+ * densities on constructed fields), invariants (mass conservation, uniform flow, rigid isometry,
+ * the steady velocity-inlet channel), special cases (integer-shift transfer, quarter-turn
+ * permutation), transpose identities and central finite differences of J.  The Taylor-Couette
+ * comparison of the paper's Appendix is a physics check within the penalisation error.
+ * or_step_T_paper (the paper's own adjoint form) is PARITY UNPINNED: it is the derivative of no
+ * discrete map; it is checked only where it must equal the exact step and against central
+ * differences within the paper's own "agree fairly".
  *
  * Layout: node (i,j,k) has index i + n0*(j + n1*k).  Vector fields are component-major:
  * u[a*ncell + idx].  2D problems use n[2] = nd[2] = 1 and only the x,y components.
