@@ -578,7 +578,7 @@ int launch_adj_dev(lks_ctx *c, const lks::AdjArgs<T> *dargs, const lks::SensArgs
         Timed t(c, 1, c->stream);
         e = c->d.dim == 2
                 ? lks::launch_adj2d_batch<T>(dargs, c->tile0, 1, lks::tiles2d(c->L.g), c->stream)
-                : lks::launch_adj3d_batch<T>(dargs, c->tile0, (c->L.ncell + lks::kBlockHost - 1) / lks::kBlockHost,
+                : lks::launch_adj3d_batch<T>(dargs, c->tile0, lks::prep_blocks3(c->L.ncell),
                                              c->tile0, lks::tiles3d_adj(c->L.g, (int)c->L.esz), 1,
                                              c->d.lattice, c->L.g.per[2] != 0, c->stream);
     }
@@ -1417,7 +1417,7 @@ int plan_step(lks_ctx *c, RoundLists<T> &R, int *rc) {
             R.adj[li].push_back(make_adj_args<T>(c, n, j, cs.acur));
             if (scan_adj_step(n)) R.scans.push_back({c, R.adj[li].back().Pout, R.adj[li].back().Vout[0], n, 1});
             R.atiles[li].push_back(adj_tiles(c));
-            R.ablk[li].push_back((L.ncell + lks::kBlockHost - 1) / lks::kBlockHost);
+            R.ablk[li].push_back(lks::prep_blocks3(L.ncell));  // 3D pointwise adjoint blocks
             R.sens.push_back(make_sens_args<T>(c, n));
             R.sblk.push_back((L.nd + lks::kBlockHost - 1) / lks::kBlockHost);
             cs.acur = 1 - cs.acur;

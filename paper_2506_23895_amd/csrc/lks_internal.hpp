@@ -206,4 +206,16 @@ int choose_zc3(const Geom &g, int esz);   // z planes per block of the 3D forwar
 int choose_zca3(const Geom &g, int esz);  // ... of the z-marching adjoint (after zc is set)
 long long tiles3d_adj(const Geom &g, int esz);
 
+// 64-node segments per wave of the 3D pointwise adjoint kernel: up to 8 where the grid still gives
+// at least 8192 waves (about one per wave slot of the chip), fewer on smaller grids, at least 1
+__host__ __device__ inline int prep_rows3(long long ncell) {
+    const long long r = ncell / (64LL * 8192);
+    return r < 1 ? 1 : (r > 8 ? 8 : (int)r);
+}
+// its grid: 256-thread blocks of four waves
+__host__ __device__ inline long long prep_blocks3(long long ncell) {
+    const long long per = 256LL * prep_rows3(ncell);
+    return (ncell + per - 1) / per;
+}
+
 }  // namespace lks

@@ -15,6 +15,8 @@
 // marches along z: (P*, V*) planes (halo 3) in an LDS ring, the pull transpose and its w-weighted
 // moments rho~, u~, s~ per plane (halo 2; a ring of five s~ planes), and Lambda^{n-1} of the
 // plane two behind from the transposed equilibrium and the transposed strain operator.
+#include <type_traits>
+
 #include "lks_device.hpp"
 
 namespace lks {
@@ -294,7 +296,11 @@ __device__ __forceinline__ void fwd3d_body(const FwdArgs<T> &a, int bx, int by, 
         fetch_r(zc + 1);
         int zw = zc;
         const bool zin = wrapc(zw, nz, g.per[2]);
-        if (zin) {
+        // E of every slot of plane zc.  FACE: some slot of the block may sit on a non-periodic
+        // face (one-sided derivatives); blocks away from every face take the straight-line code,
+        // whose LDS reads are all issued before the arithmetic
+        auto e_pass = [&](auto face_tag) {
+            constexpr bool FACE = decltype(face_tag)::value;
             // (planes zc +- 2 only for the one-sided rows at z faces, never in a z-periodic ring)
             const int s0 = uring<PZ>(zc), sm1 = uring<PZ>(zc - 1), sp1 = uring<PZ>(zc + 1),
                       sm2 = uring<PZ>(zc - 2), sp2 = uring<PZ>(zc + 2);
@@ -311,13 +317,15 @@ __device__ __forceinline__ void fwd3d_body(const FwdArgs<T> &a, int bx, int by, 
                     du[c][0] = T(0.5) * (p[c0 + 1] - p[c0 - 1]);
                     du[c][1] = T(0.5) * (p[c0 + UX] - p[c0 - UX]);
                     du[c][2] = T(0.5) * (su[sp1][c][c0] - su[sm1][c][c0]);
-                    if (xface && (efl[k] & 3))
-                        du[c][0] = (efl[k] & 1) ? d_lo(u[c], p[c0 + 1], p[c0 + 2]) : d_hi(u[c], p[c0 - 1], p[c0 - 2]);
-                    if (yface && (efl[k] & 12))
-                        du[c][1] = (efl[k] & 4) ? d_lo(u[c], p[c0 + UX], p[c0 + 2 * UX])
-                                                : d_hi(u[c], p[c0 - UX], p[c0 - 2 * UX]);
-                    if (zlo) du[c][2] = d_lo(u[c], su[sp1][c][c0], su[sp2][c][c0]);
-                    if (zhi) du[c][2] = d_hi(u[c], su[sm1][c][c0], su[sm2][c][c0]);
+                    if constexpr (FACE) {
+                        if (xface && (efl[k] & 3))
+                            du[c][0] = (efl[k] & 1) ? d_lo(u[c], p[c0 + 1], p[c0 + 2]) : d_hi(u[c], p[c0 - 1], p[c0 - 2]);
+                        if (yface && (efl[k] & 12))
+                            du[c][1] = (efl[k] & 4) ? d_lo(u[c], p[c0 + UX], p[c0 + 2 * UX])
+                                                    : d_hi(u[c], p[c0 - UX], p[c0 - 2 * UX]);
+                        if (zlo) du[c][2] = d_lo(u[c], su[sp1][c][c0], su[sp2][c][c0]);
+                        if (zhi) du[c][2] = d_hi(u[c], su[sm1][c][c0], su[sm2][c][c0]);
+                    }
                 }
                 const T a0 = rcur[k] - T(1.5) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
                 T tt[3][3];
@@ -330,8 +338,6 @@ __device__ __forceinline__ void fwd3d_body(const FwdArgs<T> &a, int bx, int by, 
                 // +c and -c share the even part a0 + c.T.c; the odd part 3 c.u changes sign
 #pragma unroll
                 for (int q = 1; q < Q; ++q) {
-                    constexpr int dummy = 0;
-                    (void)dummy;
                     if (opp<Q>(q) < q) continue;
                     const int cx = cq<Q>(q, 0), cy = cq<Q>(q, 1), cz = cq<Q>(q, 2);
                     // c.T.c and c.u over the non-zero components of c only (|c_b| <= 1): a product
@@ -343,15 +349,20 @@ __device__ __forceinline__ void fwd3d_body(const FwdArgs<T> &a, int bx, int by, 
                     if (cx && cy) ev += T(2 * cx * cy) * tt[0][1];
                     if (cx && cz) ev += T(2 * cx * cz) * tt[0][2];
                     if (cy && cz) ev += T(2 * cy * cz) * tt[1][2];
-                    T cu = T(0);
-                    if (cx) cu += T(cx) * u[0];
-                    if (cy) cu += T(cy) * u[1];
-                    if (cz) cu += T(cz) * u[2];
+                    // (built from its first non-zero term: 0 + x is not folded to x either)
+                    T cu = cx ? T(cx) * u[0] : T(0);
+                    if (cy) cu = cx ? cu + T(cy) * u[1] : T(cy) * u[1];
+                    if (cz) cu = (cx || cy) ? cu + T(cz) * u[2] : T(cz) * u[2];
                     const T od = T(3) * cu;
                     sE[q - 1][i] = T(wq<Q>(q)) * (ev + od);
                     sE[opp<Q>(q) - 1][i] = T(wq<Q>(q)) * (ev - od);
                 }
             }
+        };
+        if (zin) {
+            const bool zface = !g.per[2] && (zw == 0 || zw == nz - 1);
+            if (xface || yface || zface) e_pass(std::true_type{});
+            else e_pass(std::false_type{});
         }
         // the rest population of the own node, from its own rho and u (the commit below
         // replaces plane zc - NR / 2, not plane zc)
@@ -597,26 +608,10 @@ __device__ __forceinline__ void adj3d_prep_row(const AdjArgs<T> &a, int x0, int 
     }
 }
 
+// One node of the pointwise part, any boundary configuration (t: the node's linear index)
 template <typename T>
-__device__ __forceinline__ void adj3d_prep_body(const AdjArgs<T> &a, long long blk) {
+__device__ __forceinline__ void adj3d_prep_node(const AdjArgs<T> &a, long long t) {
     const Geom &g = a.g;
-    const long long ncell = (long long)g.n[0] * g.n[1] * g.n[2];
-    {   // wave-uniform row test for the fast path
-        const long long tw = blk * kBlock + 64 * __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-        const unsigned twu = (unsigned)tw, n0 = (unsigned)g.n[0], n1 = (unsigned)g.n[1];
-        const int x0 = (int)(twu % n0), y = (int)((twu / n0) % n1), z = (int)(twu / (n0 * n1));
-        const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
-        const bool row = tw + 63 < ncell && x0 + 63 < nx;
-        const bool yok = g.per[1] || (y >= 2 && y <= ny - 3);
-        const bool zok = g.per[2] || (z >= 2 && z <= nz - 3);
-        const bool xok = g.per[0] || (x0 != 1 && x0 + 63 != nx - 2);  // a face next to the wave's ends
-        if (row && yok && zok && xok) {
-            adj3d_prep_row<T>(a, x0, y, z);
-            return;
-        }
-    }
-    const long long t = blk * kBlock + threadIdx.x;
-    if (t >= ncell) return;
     const unsigned tu = (unsigned)t, n0 = (unsigned)g.n[0], n1 = (unsigned)g.n[1];  // < 2^31 cells
     const int x = (int)(tu % n0), y = (int)((tu / n0) % n1), z = (int)(tu / (n0 * n1));
     const long long idx = x + y * g.sy + z * g.sz;
@@ -662,6 +657,46 @@ __device__ __forceinline__ void adj3d_prep_body(const AdjArgs<T> &a, long long b
         if (a.obj.active && obj_uses_kappa(a.obj.kind) && (!a.obj.mask || a.obj.mask[idx]))
             kb += a.obj.scale * obj_dkappa(a.obj, x, y, z, uu, uss);
         a.kbar[bi] = (T)kb;
+    }
+}
+
+// A wave takes prep_rows3(ncell) consecutive 64-node segments of the linear node order, so its
+// uniform work (argument loads, the segment's coordinates, the fast-path test) is paid once per
+// segment with coordinates advanced by additions instead of divisions.
+template <typename T>
+__device__ __forceinline__ void adj3d_prep_body(const AdjArgs<T> &a, long long blk) {
+    const Geom &g = a.g;
+    const long long ncell = (long long)g.n[0] * g.n[1] * g.n[2];
+    const int rows = prep_rows3(ncell);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    long long tw = (blk * (kBlock / 64) + wave) * 64LL * rows;
+    if (tw >= ncell) return;
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const unsigned n0 = (unsigned)nx, n1 = (unsigned)ny;
+    int x0, y, z;
+    {
+        const unsigned twu = (unsigned)tw;  // < 2^31 cells
+        x0 = (int)(twu % n0);
+        y = (int)((twu / n0) % n1);
+        z = (int)(twu / (n0 * n1));
+    }
+    const int lane = threadIdx.x & 63;
+    for (int r = 0; r < rows && tw < ncell; ++r, tw += 64) {
+        // wave-uniform row test for the fast path
+        const bool row = tw + 63 < ncell && x0 + 63 < nx;
+        const bool yok = g.per[1] || (y >= 2 && y <= ny - 3);
+        const bool zok = g.per[2] || (z >= 2 && z <= nz - 3);
+        const bool xok = g.per[0] || (x0 != 1 && x0 + 63 != nx - 2);  // a face next to the wave's ends
+        if (row && yok && zok && xok) adj3d_prep_row<T>(a, x0, y, z);
+        else if (tw + lane < ncell) adj3d_prep_node<T>(a, tw + lane);
+        x0 += 64;
+        while (x0 >= nx) {
+            x0 -= nx;
+            if (++y == ny) {
+                y = 0;
+                ++z;
+            }
+        }
     }
 }
 
@@ -735,22 +770,44 @@ __device__ __forceinline__ void adj3d_main_body(const AdjArgs<T> &a, int bx, int
     const int ze = min(zs + g.zca, nz);
     const int ox = tid % TX, oy = tid / TX;
 
+    // (P*, V*) plane slots of this thread (x, y wrapped; -1 off the domain), computed once
+    long long poff[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int i = tid + k * NT;
+        poff[k] = -1;
+        if (i >= PP) continue;
+        int gx = x0 - 3 + i % PX, gy = y0 - 3 + i / PX;
+        if (wrapc(gx, nx, g.per[0]) && wrapc(gy, ny, g.per[1])) poff[k] = gx + (long long)gy * g.sy;
+    }
+    const LKS_GLOBAL T *__restrict__ ps = gld(a.Ps);
+    const LKS_GLOBAL T *__restrict__ vs0 = gld(a.Vs[0]);
+    const LKS_GLOBAL T *__restrict__ vs1 = gld(a.Vs[1]);
+    const LKS_GLOBAL T *__restrict__ vs2 = gld(a.Vs[2]);
+    const LKS_GLOBAL T *__restrict__ up0 = gld(a.uprev[0]);
+    const LKS_GLOBAL T *__restrict__ up1 = gld(a.uprev[1]);
+    const LKS_GLOBAL T *__restrict__ up2 = gld(a.uprev[2]);
+    LKS_GLOBAL T *__restrict__ pout = gst(a.Pout);
+    LKS_GLOBAL T *__restrict__ vout0 = gst(a.Vout[0]);
+    LKS_GLOBAL T *__restrict__ vout1 = gst(a.Vout[1]);
+    LKS_GLOBAL T *__restrict__ vout2 = gst(a.Vout[2]);
+    const long long sz = g.sz;
+    // loads are unconditional (slots off the domain read element 0 and select zero), so a plane's
+    // loads stay in flight across the moment pass instead of draining where a branch rejoins
     T preg[NP][4];
     auto fetch_pv = [&](int zp) {
         int zw = zp;
         const bool zin = wrapc(zw, nz, g.per[2]);
+        const long long zo = zin ? (long long)zw * sz : 0;
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
-            const int i = tid + k * NT;
-            preg[k][0] = preg[k][1] = preg[k][2] = preg[k][3] = T(0);
-            if (i >= PP || !zin) continue;
-            int gx = x0 - 3 + i % PX, gy = y0 - 3 + i / PX;
-            if (!wrapc(gx, nx, g.per[0]) || !wrapc(gy, ny, g.per[1])) continue;
-            const long long idx = gx + gy * g.sy + zw * g.sz;
-            preg[k][0] = a.Ps[idx];
-            preg[k][1] = a.Vs[0][idx];
-            preg[k][2] = a.Vs[1][idx];
-            preg[k][3] = a.Vs[2][idx];
+            const bool ok = zin && poff[k] >= 0;
+            const long long o = ok ? poff[k] + zo : 0;
+            const T v0 = ps[o], v1 = vs0[o], v2 = vs1[o], v3 = vs2[o];
+            preg[k][0] = ok ? v0 : T(0);
+            preg[k][1] = ok ? v1 : T(0);
+            preg[k][2] = ok ? v2 : T(0);
+            preg[k][3] = ok ? v3 : T(0);
         }
     };
     auto commit_pv = [&](int zp) {
@@ -763,32 +820,91 @@ __device__ __forceinline__ void adj3d_main_body(const AdjArgs<T> &a, int bx, int
                 for (int c = 0; c < 4; ++c) spv[sl][c][i] = preg[k][c];
         }
     };
-    // moments of the pull transpose at moment-plane node (lx, ly) of plane zm
+    // moments of the pull transpose at moment-plane node (lx, ly) of plane zm: with
+    // e_q = P*(x + c_q) + c_q.V*(x + c_q), rho~ = sum w_q e_q, u~ = sum w_q c_q e_q and
+    // s~_ab = sum w_q c_qa c_qb e_q.  The directions are summed by kind: a +-pair along an axis gives
+    // its sum and difference, the four edges of a coordinate plane (D3Q19) and the eight corners
+    // (D3Q15) their sums with every sign pattern (butterflies), so each e_q is formed once and
+    // each moment is a short combination of these sums
     auto moments = [&](int zm, int lx, int ly, T m[10]) {
+        const int s0 = ring3(zm), sm = ring3(zm - 1), sp = ring3(zm + 1);
+        const int b0 = (ly + 1) * PX + (lx + 1);
+        auto P = [&](int sl, int dx, int dy) -> T { return spv[sl][0][b0 + dy * PX + dx]; };
+        auto V = [&](int sl, int c, int dx, int dy) -> T { return spv[sl][1 + c][b0 + dy * PX + dx]; };
+        const T w0 = T(wq<Q>(0)), w1 = T(wq<Q>(1));
+        const T fxp = P(s0, 1, 0) + V(s0, 0, 1, 0), fxm = P(s0, -1, 0) - V(s0, 0, -1, 0);
+        const T fyp = P(s0, 0, 1) + V(s0, 1, 0, 1), fym = P(s0, 0, -1) - V(s0, 1, 0, -1);
+        const T fzp = P(sp, 0, 0) + V(sp, 2, 0, 0), fzm = P(sm, 0, 0) - V(sm, 2, 0, 0);
+        const T sfx = fxp + fxm, dfx = fxp - fxm, sfy = fyp + fym, dfy = fyp - fym;
+        const T sfz = fzp + fzm, dfz = fzp - fzm;
+        const T p0 = P(s0, 0, 0);
+        // the four sums of e(+ +), e(+ -), e(- +), e(- -) with signs 1, s_a, s_b, s_a s_b
+        auto quad = [](T epp, T epm, T emp, T emm, T &S, T &Sa, T &Sb, T &Sab) {
+            const T a = epp + epm, bb = emp + emm, c = epp - epm, d = emp - emm;
+            S = a + bb;
+            Sa = a - bb;
+            Sb = c + d;
+            Sab = c - d;
+        };
+        if constexpr (Q == 19) {
+            const T w2 = T(wq<Q>(7));
+            T xy, xy_x, xy_y, xy_xy, xz, xz_x, xz_z, xz_xz, yz, yz_y, yz_z, yz_yz;
+            {   // edges (+-1, +-1, 0): plane zm
+                const T epp = P(s0, 1, 1) + V(s0, 0, 1, 1) + V(s0, 1, 1, 1);
+                const T epm = P(s0, 1, -1) + V(s0, 0, 1, -1) - V(s0, 1, 1, -1);
+                const T emp = P(s0, -1, 1) - V(s0, 0, -1, 1) + V(s0, 1, -1, 1);
+                const T emm = P(s0, -1, -1) - V(s0, 0, -1, -1) - V(s0, 1, -1, -1);
+                quad(epp, epm, emp, emm, xy, xy_x, xy_y, xy_xy);
+            }
+            {   // edges (+-1, 0, +-1): planes zm +- 1
+                const T epp = P(sp, 1, 0) + V(sp, 0, 1, 0) + V(sp, 2, 1, 0);
+                const T epm = P(sm, 1, 0) + V(sm, 0, 1, 0) - V(sm, 2, 1, 0);
+                const T emp = P(sp, -1, 0) - V(sp, 0, -1, 0) + V(sp, 2, -1, 0);
+                const T emm = P(sm, -1, 0) - V(sm, 0, -1, 0) - V(sm, 2, -1, 0);
+                quad(epp, epm, emp, emm, xz, xz_x, xz_z, xz_xz);
+            }
+            {   // edges (0, +-1, +-1)
+                const T epp = P(sp, 0, 1) + V(sp, 1, 0, 1) + V(sp, 2, 0, 1);
+                const T epm = P(sm, 0, 1) + V(sm, 1, 0, 1) - V(sm, 2, 0, 1);
+                const T emp = P(sp, 0, -1) - V(sp, 1, 0, -1) + V(sp, 2, 0, -1);
+                const T emm = P(sm, 0, -1) - V(sm, 1, 0, -1) - V(sm, 2, 0, -1);
+                quad(epp, epm, emp, emm, yz, yz_y, yz_z, yz_yz);
+            }
+            m[0] = w0 * p0 + w1 * (sfx + sfy + sfz) + w2 * (xy + xz + yz);
+            m[1] = w1 * dfx + w2 * (xy_x + xz_x);
+            m[2] = w1 * dfy + w2 * (xy_y + yz_y);
+            m[3] = w1 * dfz + w2 * (xz_z + yz_z);
+            m[4] = w1 * sfx + w2 * (xy + xz);
+            m[5] = w1 * sfy + w2 * (xy + yz);
+            m[6] = w1 * sfz + w2 * (xz + yz);
+            m[7] = w2 * xy_xy;
+            m[8] = w2 * xz_xz;
+            m[9] = w2 * yz_yz;
+        } else {  // D3Q15: the eight corners (+-1, +-1, +-1)
+            const T w3 = T(wq<Q>(7));
+            T S[2], Sx[2], Sy[2], Sxy[2];  // per z sign (0: +1, 1: -1)
 #pragma unroll
-        for (int c = 0; c < 10; ++c) m[c] = T(0);
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int cx = cq<Q>(q, 0), cy = cq<Q>(q, 1), cz = cq<Q>(q, 2);
-            const int sl = ring3(zm + cz);
-            const int pi = (ly + 1 + cy) * PX + (lx + 1 + cx);
-            // only the non-zero components of c (|c_b| <= 1) contribute: a product with a zero
-            // coefficient is not folded away in IEEE arithmetic, and its LDS read is skipped too
-            T eb = spv[sl][0][pi];
-            if (cx) eb += T(cx) * spv[sl][1][pi];
-            if (cy) eb += T(cy) * spv[sl][2][pi];
-            if (cz) eb += T(cz) * spv[sl][3][pi];
-            const T we = T(wq<Q>(q)) * eb;
-            m[0] += we;                            // rho~
-            if (cx) m[1] += T(cx) * we;            // u~
-            if (cy) m[2] += T(cy) * we;
-            if (cz) m[3] += T(cz) * we;
-            if (cx) m[4] += we;                    // s~ xx, yy, zz, xy, xz, yz
-            if (cy) m[5] += we;
-            if (cz) m[6] += we;
-            if (cx && cy) m[7] += T(cx * cy) * we;
-            if (cx && cz) m[8] += T(cx * cz) * we;
-            if (cy && cz) m[9] += T(cy * cz) * we;
+            for (int h = 0; h < 2; ++h) {
+                const int sl = h == 0 ? sp : sm;
+                const T sz = h == 0 ? T(1) : T(-1);
+                const T epp = P(sl, 1, 1) + V(sl, 0, 1, 1) + V(sl, 1, 1, 1) + sz * V(sl, 2, 1, 1);
+                const T epm = P(sl, 1, -1) + V(sl, 0, 1, -1) - V(sl, 1, 1, -1) + sz * V(sl, 2, 1, -1);
+                const T emp = P(sl, -1, 1) - V(sl, 0, -1, 1) + V(sl, 1, -1, 1) + sz * V(sl, 2, -1, 1);
+                const T emm = P(sl, -1, -1) - V(sl, 0, -1, -1) - V(sl, 1, -1, -1) + sz * V(sl, 2, -1, -1);
+                quad(epp, epm, emp, emm, S[h], Sx[h], Sy[h], Sxy[h]);
+            }
+            const T c = S[0] + S[1], cx = Sx[0] + Sx[1], cy = Sy[0] + Sy[1], cz = S[0] - S[1];
+            const T cxz = Sx[0] - Sx[1], cyz = Sy[0] - Sy[1], cxy = Sxy[0] + Sxy[1];
+            m[0] = w0 * p0 + w1 * (sfx + sfy + sfz) + w3 * c;
+            m[1] = w1 * dfx + w3 * cx;
+            m[2] = w1 * dfy + w3 * cy;
+            m[3] = w1 * dfz + w3 * cz;
+            m[4] = w1 * sfx + w3 * c;
+            m[5] = w1 * sfy + w3 * c;
+            m[6] = w1 * sfz + w3 * c;
+            m[7] = w3 * cxy;
+            m[8] = w3 * cxz;
+            m[9] = w3 * cyz;
         }
     };
 
@@ -818,8 +934,18 @@ __device__ __forceinline__ void adj3d_main_body(const AdjArgs<T> &a, int bx, int
         dcy[o] = deriv_T3(f, gyo, ny, g.per[1]);
     }
 
-    for (int zm = zfirst; zm <= ze - 1 + LAG; ++zm) {
+    const bool col_ok = gxo < nx && gyo < ny;
+    const long long ocol = gxo + (long long)gyo * g.sy;
+    // the plane loop is uniform over the block (bounds through readfirstlane, so that the
+    // compiler keeps its counter and every per-plane index in scalar registers)
+    const int zm0 = __builtin_amdgcn_readfirstlane(zfirst), zm1 = __builtin_amdgcn_readfirstlane(ze - 1 + LAG);
+    for (int zm = zm0; zm <= zm1; ++zm) {
         fetch_pv(zm + 2);  // in flight during the moment pass
+        // u^{n-1} of this thread's output node, requested before the moment pass too
+        const int zo = zm - LAG;
+        const bool oin = zo >= zs && zo < ze && col_ok;
+        const long long oidx = oin ? ocol + (long long)zo * sz : 0;
+        const T uq0 = up0[oidx], uq1 = up1[oidx], uq2 = up2[oidx];
         int zw = zm;
         const bool zin = wrapc(zw, nz, g.per[2]);
         {   // own column first, then one pass over the halo ring
@@ -860,17 +986,15 @@ __device__ __forceinline__ void adj3d_main_body(const AdjArgs<T> &a, int bx, int
         }
         __syncthreads();
         commit_pv(zm + 2);  // replaces plane zm - 1, no longer read
-        const int zo = zm - LAG;
-        const int gx = x0 + ox, gy = y0 + oy;
-        if (zo >= zs && zo < ze && gx < nx && gy < ny) {
-            const long long idx = gx + gy * g.sy + zo * g.sz;
+        if (oin) {
+            const long long idx = oidx;
             const int c0 = (oy + 2) * MX + (ox + 2);
             const T rt = ru[2 - LAG][0];
             const T ut[3] = {ru[2 - LAG][1], ru[2 - LAG][2], ru[2 - LAG][3]};
             const T sxx = s_plane<T, PZ>(ss, 0, zo)[c0], syy = s_plane<T, PZ>(ss, 1, zo)[c0];
             const T szz = s_plane<T, PZ>(ss, 2, zo)[c0], sxy = s_plane<T, PZ>(ss, 3, zo)[c0];
             const T sxz = s_plane<T, PZ>(ss, 4, zo)[c0], syz = s_plane<T, PZ>(ss, 5, zo)[c0];
-            const T u[3] = {a.uprev[0][idx], a.uprev[1][idx], a.uprev[2][idx]};
+            const T u[3] = {uq0, uq1, uq2};
             T v[3];
             v[0] = T(3) * ut[0] + T(9) * (sxx * u[0] + sxy * u[1] + sxz * u[2]) - T(3) * rt * u[0];
             v[1] = T(3) * ut[1] + T(9) * (sxy * u[0] + syy * u[1] + syz * u[2]) - T(3) * rt * u[1];
@@ -908,10 +1032,10 @@ __device__ __forceinline__ void adj3d_main_body(const AdjArgs<T> &a, int bx, int
                 }
                 v[aa] += A2 * deriv_T3(f, zo, nz, g.per[2]);
             }
-            a.Pout[idx] = rt;
-            a.Vout[0][idx] = v[0];
-            a.Vout[1][idx] = v[1];
-            a.Vout[2][idx] = v[2];
+            pout[idx] = rt;
+            vout0[idx] = v[0];
+            vout1[idx] = v[1];
+            vout2[idx] = v[2];
         }
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
