@@ -204,6 +204,26 @@ def cpu_baseline(wl: str, cfg: dict, gamma: np.ndarray) -> dict:
             "single_thread": single_thread_rate(wl, cfg, single_steps)}
 
 
+def copy_reference(torch, dev, mib: int = 1024, reps: int = 10) -> dict:
+    """A plain device-to-device copy of `mib` MiB timed with events: the achievable HBM rate of a
+    streaming kernel on this GPU, reported beside the roofline fractions as a secondary reference."""
+    n = mib * 1024 * 1024 // 4
+    a = torch.ones(n, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    gbs = 2 * n * 4 / (ms * 1e-3) / 1e9
+    del a, b
+    return {"achieved": round(gbs, 1), "unit": "GB/s", "bytes_moved_per_copy": 2 * n * 4,
+            "ms_per_copy": round(ms, 4), "frac": round(gbs / 8000.0, 4)}
+
+
 def served_leg(n_req: int, rate: float, seed: int = 5, fill_cells: float = 0.0) -> dict:
     """Continuous batching vs back-to-back plain solves on one seeded Poisson request list."""
     from paper_2506_23895_amd.server import Request, Server, serve_plain, summarize
@@ -582,6 +602,7 @@ def main() -> int:
             if not args.no_cpu_baseline:
                 sub["cpu_baseline"] = cpu_baseline(wl, c2cfg, c2g)
             line[wl] = sub
+        line["copy_reference"] = copy_reference(torch, dev)
     if has_adj and not args.no_served:
         print(f"[bench] served leg: {args.requests} requests at {args.rate}/s", flush=True)
         line["served"] = served_leg(args.requests, args.rate, fill_cells=args.fill_cells)
