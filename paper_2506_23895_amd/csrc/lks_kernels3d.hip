@@ -726,19 +726,22 @@ __device__ __forceinline__ T deriv_T3(const T f[5], int c, int n, int per) {
     return acc;
 }
 
-// LDS of the z-marching adjoint: three (P*, V*) planes with halo 3, then the ring of s~ planes
-// (halo 2).  A domain that is not periodic in z keeps five planes of all six s~ components (the
+// LDS of the z-marching adjoint: three (P*, V*) planes with halo 3, then s~ planes (halo 2).  A
+// domain that is not periodic in z keeps a ring of five planes of all six s~ components (the
 // transposed one-sided rows at the z faces read two planes each way; outputs lag the moments by
-// two planes).  A z-periodic domain needs only the central difference along z: outputs lag by
-// one plane, s~ xz, yz, zz keep three planes and s~ xx, yy, xy two, which lets three blocks share
-// a CU instead of two.
+// two planes).  A z-periodic domain needs only the central difference along z, which reads the
+// output column's own s~ xz, yz, zz one plane each way: those three stay in the column thread's
+// registers (planes zm - 2 .. zm), and LDS holds one plane of s~ xx, yy, xy, xz, yz (the
+// components some x or y derivative reads from a neighbour), written after the output pass has
+// read the previous one.  That is 34 KB in FP32, so four blocks share a CU (51 KB and three with
+// a three-plane LDS ring).
 template <typename T>
 struct Adj3Lds {
     static constexpr int TX = Tile3<T>::TX, TY = Tile3<T>::TY;
     static constexpr int PX = TX + 6, PY = TY + 6, PP = PX * PY;  // (P*, V*) plane, halo 3
     static constexpr int MX = TX + 4, MY = TY + 4, MP = MX * MY;  // moment plane, halo 2
     static constexpr int SPV = 3 * 4 * PP;
-    static constexpr size_t bytes(bool pz) { return (size_t)(SPV + (pz ? 15 : 30) * MP) * sizeof(T); }
+    static constexpr size_t bytes(bool pz) { return (size_t)(SPV + (pz ? 5 : 30) * MP) * sizeof(T); }
 };
 
 // s~ component c (xx, yy, zz, xy, xz, yz) of moment plane z in the ring
@@ -746,9 +749,9 @@ template <typename T, bool PZ>
 __device__ __forceinline__ T *s_plane(T *ss, int c, int z) {
     constexpr int MP = Adj3Lds<T>::MP;
     if (!PZ) return ss + (ring5(z) * 6 + c) * MP;
-    // z-derivative components (zz, xz, yz: 2, 4, 5) in three planes, the others in two
-    if (c == 2 || c == 4 || c == 5) return ss + (ring3(z) * 3 + (c == 2 ? 0 : c - 3)) * MP;
-    return ss + (9 + (z & 1) * 3 + (c == 3 ? 2 : c)) * MP;
+    // z-periodic: one plane of xx, yy, xy, xz, yz (zz is never read from LDS)
+    (void)z;
+    return ss + (c < 2 ? c : c - 1) * MP;
 }
 
 template <typename T, int Q, bool PZ>
@@ -917,6 +920,15 @@ __device__ __forceinline__ void adj3d_main_body(const AdjArgs<T> &a, int bx, int
     T ru[3][4];  // rho~, u~ of the own column for planes zm-2, zm-1, zm
 #pragma unroll
     for (int t = 0; t < 3; ++t) ru[t][0] = ru[t][1] = ru[t][2] = ru[t][3] = T(0);
+    // z-periodic layout: s~ xz, yz, zz of the own column for planes zm-2, zm-1, zm, and this
+    // plane's LDS components (xx, yy, xy, xz, yz) of the own column and of the halo node, stored
+    // after the output pass
+    T zr[3][3], own5[5], halo5[5];
+    int hidx = 0;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) zr[t][0] = zr[t][1] = zr[t][2] = T(0);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) own5[c] = halo5[c] = T(0);
     const T A2 = T(2) * a.A;
 
     // transposed x- and y-derivatives of s~ at this thread's output column: central where every
@@ -955,8 +967,19 @@ __device__ __forceinline__ void adj3d_main_body(const AdjArgs<T> &a, int bx, int
             else
 #pragma unroll
                 for (int c = 0; c < 10; ++c) m[c] = T(0);
+            if constexpr (PZ) {
+                own5[0] = m[4];
+                own5[1] = m[5];
+                own5[2] = m[7];
+                own5[3] = m[8];
+                own5[4] = m[9];
+                zr[2][0] = m[8];
+                zr[2][1] = m[9];
+                zr[2][2] = m[6];
+            } else {
 #pragma unroll
-            for (int c = 0; c < 6; ++c) s_plane<T, PZ>(ss, c, zm)[ly * MX + lx] = m[4 + c];
+                for (int c = 0; c < 6; ++c) s_plane<T, PZ>(ss, c, zm)[ly * MX + lx] = m[4 + c];
+            }
             ru[2][0] = m[0];
             ru[2][1] = m[1];
             ru[2][2] = m[2];
@@ -980,8 +1003,17 @@ __device__ __forceinline__ void adj3d_main_body(const AdjArgs<T> &a, int bx, int
                 else
 #pragma unroll
                     for (int c = 0; c < 10; ++c) m[c] = T(0);
+                if constexpr (PZ) {
+                    halo5[0] = m[4];
+                    halo5[1] = m[5];
+                    halo5[2] = m[7];
+                    halo5[3] = m[8];
+                    halo5[4] = m[9];
+                    hidx = hy * MX + hx;
+                } else {
 #pragma unroll
-                for (int c = 0; c < 6; ++c) s_plane<T, PZ>(ss, c, zm)[hy * MX + hx] = m[4 + c];
+                    for (int c = 0; c < 6; ++c) s_plane<T, PZ>(ss, c, zm)[hy * MX + hx] = m[4 + c];
+                }
             }
         }
         __syncthreads();
@@ -992,7 +1024,7 @@ __device__ __forceinline__ void adj3d_main_body(const AdjArgs<T> &a, int bx, int
             const T rt = ru[2 - LAG][0];
             const T ut[3] = {ru[2 - LAG][1], ru[2 - LAG][2], ru[2 - LAG][3]};
             const T sxx = s_plane<T, PZ>(ss, 0, zo)[c0], syy = s_plane<T, PZ>(ss, 1, zo)[c0];
-            const T szz = s_plane<T, PZ>(ss, 2, zo)[c0], sxy = s_plane<T, PZ>(ss, 3, zo)[c0];
+            const T szz = PZ ? zr[1][2] : s_plane<T, PZ>(ss, 2, zo)[c0], sxy = s_plane<T, PZ>(ss, 3, zo)[c0];
             const T sxz = s_plane<T, PZ>(ss, 4, zo)[c0], syz = s_plane<T, PZ>(ss, 5, zo)[c0];
             const T u[3] = {uq0, uq1, uq2};
             T v[3];
@@ -1022,10 +1054,11 @@ __device__ __forceinline__ void adj3d_main_body(const AdjArgs<T> &a, int bx, int
                     for (int o = 0; o < 5; ++o) d += dcy[o] * py[c0 + (o - 2) * MX];
                     v[aa] += A2 * d;
                 }
-                if (PZ) {  // periodic z: the central difference reads planes zo - 1 and zo + 1 only
+                if constexpr (PZ) {  // periodic z: the central difference of planes zo -+ 1 (registers)
+                    const int kz = cz_ == 4 ? 0 : (cz_ == 5 ? 1 : 2);
                     f[0] = f[2] = f[4] = T(0);
-                    f[1] = s_plane<T, PZ>(ss, cz_, zo - 1)[c0];
-                    f[3] = s_plane<T, PZ>(ss, cz_, zo + 1)[c0];
+                    f[1] = zr[0][kz];
+                    f[3] = zr[2][kz];
                 } else {
 #pragma unroll
                     for (int o = 0; o < 5; ++o) f[o] = s_plane<T, PZ>(ss, cz_, zo + o - 2)[c0];
@@ -1043,6 +1076,19 @@ __device__ __forceinline__ void adj3d_main_body(const AdjArgs<T> &a, int bx, int
             ru[1][c] = ru[2][c];
         }
         __syncthreads();
+        if constexpr (PZ) {  // every output of plane zm - 1 is read: store plane zm (read after the next barrier)
+            const int lx = ox + 2, ly = oy + 2;
+#pragma unroll
+            for (int c = 0; c < 5; ++c) ss[c * MP + ly * MX + lx] = own5[c];
+            if (tid < NH)
+#pragma unroll
+                for (int c = 0; c < 5; ++c) ss[c * MP + hidx] = halo5[c];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                zr[0][c] = zr[1][c];
+                zr[1][c] = zr[2][c];
+            }
+        }
     }
 }
 
@@ -1094,14 +1140,16 @@ long long tiles3d_adj(const Geom &g, int esz) {
     return (long long)((g.n[0] + TX - 1) / TX) * ((g.n[1] + TY - 1) / TY) * ((g.n[2] + g.zca - 1) / g.zca);
 }
 
-// z planes per block of the z-marching adjoint.  Its LDS admits three FP32 blocks per CU (768
-// slots).  Where the forward keeps its longest chunk (a large grid), the adjoint takes the number
+// z planes per block of the z-marching adjoint.  Its LDS admits four FP32 blocks per CU when the
+// domain is periodic in z (1024 slots), else two.  Where the forward keeps its longest chunk (a
+// large grid), the adjoint takes the number
 // of chunks (at most the forward's) that minimises rounds x (planes + 3): the blocks of a round
-// run together, and a block marches about 3 planes beyond its chunk.  On 256^3 this picks 86
-// planes (one round), and the measured launch times follow the model's order: 86 planes 469 us,
-// 43 planes 477, 29 planes 489, 32 planes 506.  Elsewhere, and in FP64, the forward's chunk.
+// run together, and a block marches about 3 planes beyond its chunk.  On 256^3 this picks 64
+// planes (1024 blocks, one round).  With three blocks per CU the measured launch times followed
+// the model's order (86 planes 469 us, 43 planes 477, 29 planes 489, 32 planes 506).  Elsewhere,
+// and in FP64, the forward's chunk.
 int choose_zca3(const Geom &g, int esz) {
-    constexpr long long kAdjSlots = 768;
+    const long long kAdjSlots = g.per[2] ? 1024 : 512;
     if (esz != 4 || g.zc < Tile3<float>::ZC) return g.zc;
     const long long cols = (long long)((g.n[0] + Tile3<float>::TX - 1) / Tile3<float>::TX) *
                            ((g.n[1] + Tile3<float>::TY - 1) / Tile3<float>::TY);
