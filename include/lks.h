@@ -139,6 +139,14 @@ typedef struct {
     size_t hbm_budget_bytes;     /* 0 = no budget; else lks_create fails with LKS_ENOMEM above it */
     int adjoint_form;            /* LKS_ADJ_EXACT (0) or LKS_ADJ_PAPER; PAPER needs dim 2 and is
                                     not served by lks_begin (LKS_EUNSUPPORTED) */
+    int zchunk;                  /* 3D: z planes each block of the z-marching kernels takes.  0
+                                    chooses from the grid for a job alone on the GPU (enough blocks
+                                    to fill it, at least 8 planes); a value in [8, 32] is taken as
+                                    is (evened out over the chunks of n[2]), for jobs that share
+                                    the GPU in batched rounds, where longer chunks re-evaluate
+                                    fewer halo planes.  It changes only the grouping of the
+                                    per-block objective partials (J to FP64 rounding); the state
+                                    and dJ/dgamma are the same.  Outside [8, 32]: LKS_EINVAL. */
 } lks_desc;
 
 typedef struct lks_ctx lks_ctx;

@@ -91,6 +91,8 @@ int plan(const lks_desc *d, Layout &L, std::string *err) {
         return fail(err, LKS_EINVAL, "unknown adjoint form");
     if (d->adjoint_form == LKS_ADJ_PAPER && d->dim != 2)
         return fail(err, LKS_EUNSUPPORTED, "the paper's adjoint form is built for 2D");
+    if (d->zchunk != 0 && (d->zchunk < 8 || d->zchunk > 32))
+        return fail(err, LKS_EINVAL, "zchunk must be 0 or in [8, 32]");
     if (!std::isfinite(d->rho0) || !finite3(d->u0) || !finite3(d->body_force) || !finite3(d->xi_G))
         return fail(err, LKS_EINVAL, "non-finite initial state, force or xi_G");
 
@@ -138,6 +140,10 @@ int plan(const lks_desc *d, Layout &L, std::string *err) {
     L.nd = (long long)d->nd[0] * d->nd[1] * d->nd[2];
     L.esz = d->precision == LKS_F64 ? 8 : 4;
     g.zc = D == 3 ? lks::choose_zc3(g, (int)L.esz) : 1;
+    if (D == 3 && d->zchunk > 0) {  // the caller's chunk, evened out over the chunks of n_z
+        const int nch = (g.n[2] + d->zchunk - 1) / d->zchunk;
+        g.zc = (g.n[2] + nch - 1) / nch;
+    }
     g.zca = D == 3 ? lks::choose_zca3(g, (int)L.esz) : 1;
     const int N = d->nsteps;
     L.fwd_only = d->objective.kind == LKS_OBJ_NONE;  // nothing to differentiate: no reverse buffers

@@ -63,7 +63,7 @@ class LksDesc(C.Structure):
         ("body_force", C.c_double * 3), ("nsteps", C.c_int), ("motion", C.POINTER(LksMotion)),
         ("objective", LksObjective), ("precision", C.c_int), ("checkpoint_every", C.c_int),
         ("io_on_device", C.c_int), ("stream", C.c_void_p), ("hbm_budget_bytes", C.c_size_t),
-        ("adjoint_form", C.c_int),
+        ("adjoint_form", C.c_int), ("zchunk", C.c_int),
     ]
 
 
@@ -181,6 +181,7 @@ class _DescHolder:
         d.stream = stream
         d.hbm_budget_bytes = int(hbm_budget)
         d.adjoint_form = _ADJ[cfg.get("adjoint", "EXACT")]
+        d.zchunk = int(cfg.get("zchunk", 0))
         self.d = d
 
 

@@ -108,15 +108,22 @@ class Server:
     """fill_cells > 0: each round advances only the admitted jobs with the least remaining work
     (cells x micro-steps left), as many as it takes to reach fill_cells cells in the round, so that
     short jobs finish first instead of sharing every round with long ones, and every job at least
-    once every max_wait rounds; 0 advances every admitted job every round."""
+    once every max_wait rounds; 0 advances every admitted job every round.
+
+    zchunk > 0: 3D jobs that do not set their own take z chunks of that many planes (8..32; the
+    lks_desc field of that name).  A lone job's chunk is chosen to fill the GPU by itself; in a
+    batch the other jobs fill it, and longer chunks re-evaluate fewer halo planes per block.  Such
+    a job's dJ/dgamma is bitwise the one of a Solver given the same zchunk, and its J differs from
+    the default only in the FP64 rounding of the per-block partial sums."""
 
     def __init__(self, hbm_budget: int = 0, max_active: int = 32, fill_cells: float = 0.0,
-                 max_wait: int = 64):
+                 max_wait: int = 64, zchunk: int = 0):
         free, total = torch.cuda.mem_get_info()
         self.budget = int(hbm_budget) if hbm_budget else int(0.8 * free)
         self.max_active = max_active
         self.fill_cells = float(fill_cells)
         self.max_wait = int(max_wait)
+        self.zchunk = int(zchunk)
         self.device = torch.cuda.current_device()
         self.stream = torch.cuda.current_stream().cuda_stream
         self.batch = lks.Batch(self.stream)
@@ -204,7 +211,10 @@ class Server:
             while pending and pending[0][0].arrival <= now and len(active) < self.max_active:
                 rq, fut = pending[0]
                 try:
-                    need = lks.query_bytes(rq.cfg)
+                    cfg = rq.cfg
+                    if self.zchunk and cfg["dim"] == 3 and "zchunk" not in cfg:
+                        cfg = dict(cfg, zchunk=self.zchunk)  # the caller's request is left as it is
+                    need = lks.query_bytes(cfg)
                 except lks.LksError as e:
                     pending.pop(0)
                     finish(Result(rq.rid, float("nan"), np.empty(0), rq.arrival, now, now,
@@ -221,7 +231,7 @@ class Server:
                 pending.pop(0)
                 dt = torch.float64 if rq.cfg["precision"] == "F64" else torch.float32
                 try:
-                    s = lks.Solver(rq.cfg, io_on_device=True, stream=self.stream)
+                    s = lks.Solver(cfg, io_on_device=True, stream=self.stream)
                     g = torch.as_tensor(rq.gamma, dtype=dt).to(dev)
                     out = torch.empty_like(g)
                     s.begin(g, out)

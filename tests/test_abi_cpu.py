@@ -43,6 +43,8 @@ def test_no_cpu_fallback_in_binding():
     (lambda c: c.update(checkpoint_every=-2), lks.LKS_EINVAL),
     (lambda c: c["motion"].__setitem__((5, 0), 2.0), lks.LKS_EINVAL),           # R not orthogonal
     (lambda c: c["motion"].__setitem__((7, 12), 5.0), lks.LKS_EINVAL),          # footprint leaves
+    (lambda c: c.update(zchunk=4), lks.LKS_EINVAL),                              # z chunk below 8
+    (lambda c: c.update(zchunk=64), lks.LKS_EINVAL),                             # ... above 32
 ])
 def test_descriptor_validation(mutate, code):
     cfg = I.config_c1()

@@ -145,3 +145,34 @@ def test_submit_returns_futures_with_the_plain_results():
             gp = s.sensitivity()
         J, grad, lat = results[k]
         assert J == Jp and np.array_equal(grad, gp) and lat > 0, k
+
+
+def test_server_zchunk_keeps_the_gradient_and_matches_a_solver_with_the_same_chunk():
+    """Server(zchunk=16) gives 3D jobs 16-plane z chunks: each result is bitwise that of a Solver
+    given the same chunk; dJ/dgamma is bitwise that of the default chunk, and J differs only in the
+    FP64 rounding of the per-block partial sums."""
+    import torch
+    from paper_2506_23895_amd import lks
+    from paper_2506_23895_amd.server import Server
+    torch.cuda.set_device(0)
+    cfgs = [c for c in jobs() if c["dim"] == 3]
+    gammas = [I.gamma_field(c["nd"], c["dim"], 50 + k).astype(np.float32) for k, c in enumerate(cfgs)]
+    announce("served: zchunk 16")
+    srv = Server(zchunk=16)
+    futs = [srv.submit(c, g) for c, g in zip(cfgs, gammas)]
+    results = [f.result(timeout=300) for f in futs]
+    srv.close()
+    for k, c in enumerate(cfgs):
+        assert "zchunk" not in c  # the caller's configuration is left as it is
+        with lks.Solver(dict(c, zchunk=16)) as s:
+            J16 = s.forward(gammas[k])
+            s.adjoint()
+            g16 = s.sensitivity()
+        with lks.Solver(c) as s:
+            J0 = s.forward(gammas[k])
+            s.adjoint()
+            g0 = s.sensitivity()
+        J, grad, _ = results[k]
+        assert J == J16 and np.array_equal(grad, g16), k
+        assert np.array_equal(g16, g0), k
+        assert abs(J16 - J0) <= 1e-12 * abs(J0), (k, J16, J0)
