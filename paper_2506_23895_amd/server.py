@@ -110,9 +110,10 @@ class Server:
     short jobs finish first instead of sharing every round with long ones, and every job at least
     once every max_wait rounds; 0 advances every admitted job every round.
 
-    zchunk > 0: 3D jobs that do not set their own take z chunks of that many planes (8..32; the
-    lks_desc field of that name).  A lone job's chunk is chosen to fill the GPU by itself; in a
-    batch the other jobs fill it, and longer chunks re-evaluate fewer halo planes per block.  Such
+    zchunk > 0: 3D jobs that do not set their own and are admitted while at least three others
+    are active take z chunks of that many planes (8..32; the lks_desc field of that name).  A lone
+    job's chunk is chosen to fill the GPU by itself; in a loaded batch the other jobs fill it, and
+    longer chunks re-evaluate fewer halo planes per block.  Such
     a job's dJ/dgamma is bitwise the one of a Solver given the same zchunk, and its J differs from
     the default only in the FP64 rounding of the per-block partial sums."""
 
@@ -124,6 +125,7 @@ class Server:
         self.fill_cells = float(fill_cells)
         self.max_wait = int(max_wait)
         self.zchunk = int(zchunk)
+        self.zchunk_jobs = 4  # jobs sharing the GPU (this one included) from which zchunk applies
         self.device = torch.cuda.current_device()
         self.stream = torch.cuda.current_stream().cuda_stream
         self.batch = lks.Batch(self.stream)
@@ -212,7 +214,10 @@ class Server:
                 rq, fut = pending[0]
                 try:
                     cfg = rq.cfg
-                    if self.zchunk and cfg["dim"] == 3 and "zchunk" not in cfg:
+                    # longer z chunks only for a job admitted into a loaded GPU: alone, its own
+                    # choice fills the GPU and the longer chunk would leave it part idle
+                    if self.zchunk and cfg["dim"] == 3 and "zchunk" not in cfg and \
+                            len(active) + 1 >= self.zchunk_jobs:
                         cfg = dict(cfg, zchunk=self.zchunk)  # the caller's request is left as it is
                     need = lks.query_bytes(cfg)
                 except lks.LksError as e:

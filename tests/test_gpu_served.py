@@ -159,6 +159,7 @@ def test_server_zchunk_keeps_the_gradient_and_matches_a_solver_with_the_same_chu
     gammas = [I.gamma_field(c["nd"], c["dim"], 50 + k).astype(np.float32) for k, c in enumerate(cfgs)]
     announce("served: zchunk 16")
     srv = Server(zchunk=16)
+    srv.zchunk_jobs = 1  # every 3D job takes the chunk, however few share the GPU
     futs = [srv.submit(c, g) for c, g in zip(cfgs, gammas)]
     results = [f.result(timeout=300) for f in futs]
     srv.close()
