@@ -23,15 +23,16 @@
  * continuous-then-discretised adjoint); the readings of silent or garbled passages are listed
  * in the design notes of the repository.
  *
- * Pins: every function here except or_step_T_paper is checked in the CPU test suite against
- * closed forms (shear-wave decay, Poiseuille, Couette, the pressure-driven channel, objective
- * densities on constructed fields), invariants (mass conservation, uniform flow, rigid isometry,
- * the steady velocity-inlet channel), special cases (integer-shift transfer, quarter-turn
- * permutation), transpose identities and central finite differences of J.  The Taylor-Couette
- * comparison of the paper's Appendix is a physics check within the penalisation error.
- * or_step_T_paper (the paper's own adjoint form) is PARITY UNPINNED: it is the derivative of no
- * discrete map; it is checked only where it must equal the exact step and against central
- * differences within the paper's own "agree fairly".
+ * Pins: every function here is checked in the CPU test suite against closed forms (shear-wave
+ * decay, Poiseuille, Couette, the pressure-driven channel, objective densities on constructed
+ * fields), invariants (mass conservation, uniform flow, rigid isometry, the steady velocity-inlet
+ * channel), special cases (integer-shift transfer, quarter-turn permutation), transpose
+ * identities and central finite differences of J.  The Taylor-Couette comparison of the paper's
+ * Appendix is a physics check within the penalisation error.  or_step_T_paper (the paper's own
+ * adjoint form) is the derivative of no discrete map, so FD cannot pin it: it is pinned where it
+ * must equal the exact step, by the closed-form per-step gain of an adjoint shear wave under a
+ * uniform kappa (which separates the divided 3 u~ from the strain part that passes), and against
+ * central differences within a few per cent.
  *
  * Layout: node (i,j,k) has index i + n0*(j + n1*k).  Vector fields are component-major:
  * u[a*ncell + idx].  2D problems use n[2] = nd[2] = 1 and only the x,y components.
@@ -110,9 +111,9 @@ int or_step_T(const or_desc *d, const double *kappa, const double *uS, const dou
  * as_ex: the same as or_step_T except that (i) the Brinkman source divides only the pulled
  * velocity moment 3 u~ (carried in U3, with the objective's u-seed) by (1 + kappa), not the whole
  * adjoint velocity, and (ii) the kappa seed is -(3 u~ / (1 + kappa)) . (u - u_S), from the pulled
- * moment alone.  U3 [3*ncell] in, U3_out [3*ncell] = 3 u~ of the new level.  PARITY UNPINNED: it
- * is not the derivative of any discrete map; the CPU tests check only that it reduces to the exact
- * step where (i) and (ii) vanish and that its gradient approaches central differences. */
+ * moment alone.  U3 [3*ncell] in, U3_out [3*ncell] = 3 u~ of the new level.  Not the derivative
+ * of any discrete map; pinned by its reduction to the exact step where (i) and (ii) vanish, the
+ * closed-form gain of an adjoint shear wave under a uniform kappa, and central differences. */
 int or_step_T_paper(const or_desc *d, const double *kappa, const double *uS, const double *u_prev,
                     const double *u_cur, const double *P, const double *V, const double *U3,
                     double *P_out, double *V_out, double *U3_out, double *kbar_out);

@@ -319,9 +319,56 @@ def test_j1_j2_on_the_pressure_driven_channel():
 
 
 # ------------------------------------------------------------------------------------------
-# the paper's own adjoint form (Sec. 2.4): checked where it must coincide with the exact step, and
-# against central differences the way the paper verifies it (Sec. 2.6); parity otherwise unpinned
+# the paper's own adjoint form (Sec. 2.4): checked where it must coincide with the exact step, by
+# the closed-form gain of an adjoint shear wave under a uniform kappa, and against central
+# differences the way the paper verifies it (Sec. 2.6)
 # ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("axis", [0, 1])
+@pytest.mark.parametrize("nu,kap", [(0.05, 0.3), (0.12, 2.0), (0.3, 0.7)])
+def test_paper_adjoint_shear_wave_gain_closed_form(axis, nu, kap):
+    """Fluid at rest, uniform kappa, periodic box, an adjoint velocity W sin(k y) along x (or the
+    same rotated).  Worked out by hand for D2Q9: the pull transpose gives 3 u~ = g1 W with
+    g1 = 1 - (1 - cos k)/3 and no rho~; the strain transpose adds g2 W with g2 = (A/9)(1 - cos 2k).
+    The exact transpose divides the whole adjoint velocity by (1 + kappa) first, so its gain is
+    (g1 + g2)/(1 + kappa).  The paper's form (Eq. au_ex) divides only the carried 3 u~, so with
+    W_n = U3_n/(1 + kappa) + (V_n - U3_n) it advances V = (g1 + g2) W, U3 = g1 W, and W gains
+    g1/(1 + kappa) + g2 per step; its kappa seed is -(U3/(1 + kappa)).(u - u_S)."""
+    L = 16
+    n = (L, 5) if axis == 0 else (5, L)  # the wave varies along `axis`, the velocity is across it
+    nc = n[0] * n[1]
+    cfg = _obj_cfg("NONE", n=n)
+    cfg["nu"] = nu
+    comp = 1 - axis
+    coord = np.array(np.unravel_index(np.arange(nc), n[::-1]))[::-1][axis]
+    k = 2 * math.pi * 3 / L
+    A = 4.5 * (1.0 / 6.0 - nu)
+    g1 = 1 - (1 - math.cos(k)) / 3
+    g2 = (A / 9) * (1 - math.cos(2 * k))
+    shape = np.sin(k * coord)
+    kappa = np.full(nc, kap)
+    uS = np.zeros((3, nc)); uS[0], uS[1] = 0.02, -0.015
+    zero = np.zeros((3, nc))
+    alpha, beta = 1.0, 0.4  # V and U3 amplitudes of the level being left
+    V = np.zeros((3, nc)); V[comp] = alpha * shape
+    U3 = np.zeros((3, nc)); U3[comp] = beta * shape
+    P = np.zeros(nc)
+    Pe, Ve, _ = O.step_T(cfg, kappa, uS, zero, zero, P, V)
+    assert np.abs(Pe).max() < 1e-15 and np.abs(Ve[axis]).max() < 1e-15
+    assert np.abs(Ve[comp] - (g1 + g2) / (1 + kap) * alpha * shape).max() < 1e-14
+    W = beta / (1 + kap) + alpha - beta
+    for _ in range(4):
+        Pp, Vp, U3p, kb = O.step_T_paper(cfg, kappa, uS, zero, zero, P, V, U3)
+        expect_kb = (beta / (1 + kap)) * uS[comp, 0] * shape
+        assert np.abs(kb - expect_kb).max() < 1e-15
+        assert np.abs(Pp).max() < 1e-15 and np.abs(Vp[axis]).max() < 1e-15
+        assert np.abs(Vp[comp] - (g1 + g2) * W * shape).max() < 1e-14
+        assert np.abs(U3p[comp] - g1 * W * shape).max() < 1e-14
+        alpha, beta = (g1 + g2) * W, g1 * W
+        W_next = beta / (1 + kap) + alpha - beta
+        assert abs(W_next - (g1 / (1 + kap) + g2) * W) < 1e-15
+        W, P, V, U3 = W_next, Pp, Vp, U3p
+
+
 def test_paper_adjoint_step_reduces_to_exact_without_flow_and_viscous_term():
     """With u = 0 before the step and A = 0 (nu = 1/6) the adjoint velocity is the pulled moment
     alone (V = 3 u~), so dividing only 3 u~ by (1 + kappa) and forming the kappa seed from it is
