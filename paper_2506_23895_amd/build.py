@@ -13,6 +13,8 @@ SOURCES = ["lks_api.hip", "lks_kernels2d.hip", "lks_kernels3d.hip", "lks_kernels
            "lks_kernels2d_paper.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # kernel arguments arrive in SGPRs instead of through a first scalar load (gfx950)
+         "-mllvm", "-amdgpu-kernarg-preload-count=16",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC,
          "-Wall", "-Wno-unused-function"]
 

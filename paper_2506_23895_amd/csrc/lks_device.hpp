@@ -22,6 +22,21 @@ __device__ __forceinline__ const LKS_GLOBAL T *gld(const T *p) { return (const L
 template <typename T>
 __device__ __forceinline__ LKS_GLOBAL T *gst(T *p) { return (LKS_GLOBAL T *)p; }
 
+// Argument blocks are read through the scalar cache field by field as the code reaches them, so
+// each 64-byte line first read behind a branch costs one more memory round trip before a wave's
+// first field load.  Touching every line of the block at once puts those misses in one round trip
+// (2D forward at 1024^2: 11.5 -> 10.9 us per launch).  The 3D kernels do not take it: their
+// blocks march for hundreds of microseconds, and the 3D forward measured slower with it.
+#define LKS_CONST __attribute__((address_space(4)))
+template <int BYTES>
+__device__ __forceinline__ void touch_lines(const void *p) {
+    const LKS_CONST unsigned *q = (const LKS_CONST unsigned *)p;
+    unsigned acc = q[BYTES / 4 - 1];
+#pragma unroll
+    for (int o = 0; o < BYTES / 4; o += 16) acc |= q[o];
+    asm volatile("" ::"r"(acc));  // keeps the loads (emits no instruction)
+}
+
 // ---- lane shifts within a 64-wide wavefront (DPP wave_shr:1 / wave_shl:1; edge lanes read 0) ----
 __device__ __forceinline__ int dpp_l(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, true); }
 __device__ __forceinline__ int dpp_r(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, true); }

@@ -379,6 +379,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd2d_batch(const FwdArgs<T> *__rest
     const long long b = blockIdx.x;
     const int j = __builtin_amdgcn_readfirstlane(job_of(tile0, njobs, b));
     const FwdArgs<T> &a = args[j];
+    touch_lines<sizeof(FwdArgs<T>)>(&a);
     const long long t = njobs == 1 ? b : b - tile0[j];  // one job: tile0 = {0}
     const Fwd2dUnits u = fwd2d_units(a.g);
     const long long ns = (a.mode & FWD_STENCIL) ? (u.total + WPB - 1) / WPB : 0;
@@ -986,6 +987,7 @@ __global__ __launch_bounds__(kBlock, LKS_ADJ2D_WAVES) void k_adj2d_batch(const A
     const long long b = blockIdx.x;
     const int j = __builtin_amdgcn_readfirstlane(job_of(tile0, njobs, b));
     const AdjArgs<T> &a = args[j];
+    touch_lines<sizeof(AdjArgs<T>)>(&a);
     const long long t = njobs == 1 ? b : b - tile0[j];  // one job: tile0 = {0}
     const Adj2dUnits u = adj2d_units(a.g);
     const long long na = (u.total + WPB - 1) / WPB;
