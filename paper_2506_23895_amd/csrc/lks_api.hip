@@ -735,6 +735,9 @@ int forward_impl(lks_ctx *c, const void *gamma, double *J) {
             cur = 1 - cur;
         }
         fa[N] = make_xfer_args<T>(c, 1, fwd_loc<T>(c, 1));
+        if (D == 2)
+            for (int n = 1; n < N; ++n)  // the launch of step n prefetches that of step n + 1
+                fa[n - 1].next = reinterpret_cast<const lks::FwdArgs<T> *>(c->argdev) + n;
         if ((rc = upload_args(c, (size_t)(N + 1) * sizeof(lks::FwdArgs<T>)))) return rc;
     }
     const auto *dfa = reinterpret_cast<const lks::FwdArgs<T> *>(c->argdev);
@@ -889,6 +892,9 @@ int adjoint_impl(lks_ctx *c) {
                     cur = 1 - cur;
                 }
                 ra[nrec + seg] = make_xfer_args<T>(c, n0, rec_loc<T>(c, seg, n0));
+                if (D == 2)
+                    for (int n = n0; n < n1; ++n)  // recomputed step n prefetches step n + 1
+                        ra[n - 1].next = reinterpret_cast<const lks::FwdArgs<T> *>(c->argdev) + n;
             }
             for (int n = n1; n >= n0; --n) {
                 aa[n - 1] = make_adj_args<T>(c, n, n - seg * K, acur);
@@ -897,6 +903,9 @@ int adjoint_impl(lks_ctx *c) {
                 acur = 1 - acur;
             }
         }
+        if (D == 2 && !paper)  // the adjoint launch of step n prefetches that of step n - 1
+            for (int n = 2; n <= N; ++n)
+                aa[n - 1].next = reinterpret_cast<const lks::AdjArgs<T> *>(c->argdev + (size_t)nfa * sizeof(lks::FwdArgs<T>)) + (n - 2);
         if (D == 2 && !paper) {  // each adjoint launch also runs the gather of the step after it (kappa_bar
                        // of consecutive steps lives in alternate halves of the kappa_bar buffer)
             const auto *dsa_dev = reinterpret_cast<const lks::SensArgs<T> *>(

@@ -37,6 +37,14 @@ __device__ __forceinline__ void touch_lines(const void *p) {
     asm volatile("" ::"r"(acc));  // keeps the loads (emits no instruction)
 }
 
+// At the end of its work, one wave per XCD (blocks are dealt to the eight XCDs in turn) touches
+// the argument block of the next launch on the stream, so that launch finds it in cache instead
+// of in HBM (2D forward at 1024^2: 10.9 -> 10.6 us per launch).
+template <int BYTES>
+__device__ __forceinline__ void prefetch_next(const void *next) {
+    if (next && blockIdx.x < 8 && threadIdx.x < 64) touch_lines<BYTES>(next);
+}
+
 // ---- lane shifts within a 64-wide wavefront (DPP wave_shr:1 / wave_shl:1; edge lanes read 0) ----
 __device__ __forceinline__ int dpp_l(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, true); }
 __device__ __forceinline__ int dpp_r(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, true); }

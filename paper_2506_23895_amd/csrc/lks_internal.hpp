@@ -81,6 +81,7 @@ struct FwdArgs {
     T *knext;           // where the extra blocks write the next step's kappa and u_S
     T *usnext[3];
     ObjParams obj;
+    const void *next;   // 2D: argument block of the sweep's next step (this launch prefetches it), or null
 };
 // FWD_TRANSFER_FIRST (2D): the transfer blocks precede the stencil tiles in the launch
 enum { FWD_STENCIL = 1, FWD_TRANSFER_NEXT = 2, FWD_TRANSFER_FIRST = 4 };
@@ -115,6 +116,7 @@ struct AdjArgs {
     const T *U3in[3];
     T *U3out[3];
     T *st[3];
+    const void *next;   // 2D: argument block of the sweep's next step (this launch prefetches it), or null
 };
 
 template <typename T>

@@ -403,6 +403,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd2d_batch(const FwdArgs<T> *__rest
     // XCD-aware: each XCD takes a contiguous run of blocks (neighbouring row bands share halos)
     const long long tl = xcd_tile(ts, ns);
     fwd2d_unit<T>(a, u, tl * WPB + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
+    prefetch_next<sizeof(FwdArgs<T>)>(a.next);
 }
 
 // transposed difference operator along one axis at coordinate c: sum_r D[r][c] f(r), with f
@@ -997,6 +998,7 @@ __global__ __launch_bounds__(kBlock, LKS_ADJ2D_WAVES) void k_adj2d_batch(const A
     }
     const long long k = t * WPB + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (k < u.total) adj2d_unit<T>(a, u, k);
+    prefetch_next<sizeof(AdjArgs<T>)>(a.next);
 }
 
 long long fwd_blocks(const Geom &g, int lattice, int esz) {
