@@ -910,9 +910,12 @@ __device__ __forceinline__ void adj2d_march(const AdjArgs<T> &a, int strip, int 
 // periodic).  Everything else — the four rows next to each y face (or the wrap of a periodic y),
 // and all rows of the outer strips when x is periodic — is a general unit of RGA rows with the
 // full boundary transpose.  March units come first (they are the longest), then the outer strips'
-// general units, then the y-edge units of the marching strips.
+// general units, then the y-edge units of the marching strips.  Six rows per march: the launch
+// alone is faster at eight (14.0 against 14.9 us at 1024^2), but the reverse sweep, where the
+// segment recompute shares the GPU, is faster at six (C3 36.7 k -> 36.9 k MLUPS; 4 and 5 rows
+// slower, 10 rows slower).
 #ifndef LKS_ADJ2D_RM
-#define LKS_ADJ2D_RM 8
+#define LKS_ADJ2D_RM 6
 #endif
 constexpr int RMA = LKS_ADJ2D_RM;
 struct Adj2dUnits {
