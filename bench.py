@@ -523,7 +523,7 @@ def main() -> int:
         trace_summary(*args.trace_summary, args.workload, args.trace_command)
         return 0
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the multi-GPU "
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 (the multi-GPU "
                                    "halo-exchange design is documented, not built)"}))
         return 2
 

@@ -50,7 +50,7 @@ extern "C" {
 #define LKS_ESTATE (-3)        /* call out of order (adjoint before forward, ...)         */
 #define LKS_ENONFINITE (-4)    /* a NaN/Inf appeared in the state                         */
 #define LKS_EDEVICE (-5)       /* a HIP runtime call failed                               */
-#define LKS_EUNSUPPORTED (-6)  /* valid but not supported by this build                   */
+#define LKS_EUNSUPPORTED (-6)  /* valid but not supported by this library                 */
 
 /* ---- enumerations ----------------------------------------------------------------------- */
 enum { LKS_D2Q9 = 0, LKS_D3Q15 = 1, LKS_D3Q19 = 2 };
