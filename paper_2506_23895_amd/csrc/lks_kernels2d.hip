@@ -308,6 +308,7 @@ __device__ __forceinline__ void fwd2d_rows(const FwdArgs<T> &a, int strip, int y
 // chunk its units (inner strips, then outer ones), then the rows [yhi, ny).  Without inner strips
 // or chunks every unit is general.  Unit k owns objective partial slot k.
 constexpr int RF = 2;
+static_assert(RY >= RF && RY % RF == 0, "an outer strip's chunk of RY rows is RY / RF general units of RF rows");
 struct Fwd2dUnits {
     int nstrips, ninner, nmc, yhi, ngs, nxf, band;
     long long top, mid, total;
