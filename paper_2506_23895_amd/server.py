@@ -104,6 +104,16 @@ def select_round(jobs: Sequence, fill_cells: float, max_wait: int) -> list:
     return order[:k]
 
 
+def admitted_cfg(cfg: dict, n_active: int, zchunk: int, zchunk_jobs: int) -> dict:
+    """The configuration a request is admitted with.  A 3D request that sets no z chunk of its own
+    takes zchunk planes when, with it, at least zchunk_jobs jobs share the GPU: alone, its own
+    choice fills the GPU and the longer chunk would leave part of it idle.  The caller's dict is
+    left as it is."""
+    if zchunk and cfg["dim"] == 3 and "zchunk" not in cfg and n_active + 1 >= zchunk_jobs:
+        return dict(cfg, zchunk=zchunk)
+    return cfg
+
+
 class Server:
     """fill_cells > 0: each round advances only the admitted jobs with the least remaining work
     (cells x micro-steps left), as many as it takes to reach fill_cells cells in the round, so that
@@ -213,12 +223,7 @@ class Server:
             while pending and pending[0][0].arrival <= now and len(active) < self.max_active:
                 rq, fut = pending[0]
                 try:
-                    cfg = rq.cfg
-                    # longer z chunks only for a job admitted into a loaded GPU: alone, its own
-                    # choice fills the GPU and the longer chunk would leave it part idle
-                    if self.zchunk and cfg["dim"] == 3 and "zchunk" not in cfg and \
-                            len(active) + 1 >= self.zchunk_jobs:
-                        cfg = dict(cfg, zchunk=self.zchunk)  # the caller's request is left as it is
+                    cfg = admitted_cfg(rq.cfg, len(active), self.zchunk, self.zchunk_jobs)
                     need = lks.query_bytes(cfg)
                 except lks.LksError as e:
                     pending.pop(0)

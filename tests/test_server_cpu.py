@@ -1,8 +1,8 @@
-"""Host logic of the served path: which jobs take a micro-step in a round (shortest remaining work
-first, aged by waiting), without a GPU."""
+"""Host logic of the served path, without a GPU: which jobs take a micro-step in a round (shortest
+remaining work first, aged by waiting), and which admitted 3D jobs take the server's z chunk."""
 from dataclasses import dataclass
 
-from paper_2506_23895_amd.server import select_round
+from paper_2506_23895_amd.server import admitted_cfg, select_round
 
 
 @dataclass
@@ -55,3 +55,15 @@ def test_shortest_work_first_fills_the_round():
 def test_long_job_is_not_starved():
     assert simulate(max_wait=10**9) >= 399     # shortest-first alone: never picked
     assert simulate(max_wait=64) == 64         # picked again after at most max_wait rounds
+
+
+def test_z_chunk_only_for_3d_jobs_admitted_into_a_loaded_gpu():
+    c3, c2 = {"dim": 3, "nsteps": 10}, {"dim": 2, "nsteps": 10}
+    assert admitted_cfg(c3, 2, 16, 4) is c3               # with it, three jobs share the GPU
+    got = admitted_cfg(c3, 3, 16, 4)                       # four: the chunk applies
+    assert got == {"dim": 3, "nsteps": 10, "zchunk": 16} and "zchunk" not in c3
+    assert admitted_cfg(c2, 10, 16, 4) is c2               # 2D jobs have no z chunk
+    own = {"dim": 3, "zchunk": 8}
+    assert admitted_cfg(own, 10, 16, 4) is own             # a request's own choice stands
+    assert admitted_cfg(c3, 10, 0, 4) is c3                # zchunk 0: off
+    assert admitted_cfg(c3, 0, 16, 1)["zchunk"] == 16      # zchunk_jobs 1: every 3D job
