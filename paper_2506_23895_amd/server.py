@@ -104,6 +104,12 @@ def select_round(jobs: Sequence, fill_cells: float, max_wait: int) -> list:
     return order[:k]
 
 
+def round_fill(n_running: int, fill_cells: float, srpt_jobs: int) -> float:
+    """fill_cells of the next round: with at most srpt_jobs jobs running, a round holds only the job
+    with the least remaining work (shortest remaining processing time first), else fill_cells."""
+    return 1.0 if n_running <= srpt_jobs else fill_cells
+
+
 def admitted_cfg(cfg: dict, n_active: int, zchunk: int, zchunk_jobs: int) -> dict:
     """The configuration a request is admitted with.  A 3D request that sets no z chunk of its own
     takes zchunk planes when, with it, at least zchunk_jobs jobs share the GPU: alone, its own
@@ -120,6 +126,13 @@ class Server:
     short jobs finish first instead of sharing every round with long ones, and every job at least
     once every max_wait rounds; 0 advances every admitted job every round.
 
+    srpt_jobs > 0: while at most that many jobs are running, each round advances only the one with
+    the least remaining work (its other rounds are the ones above).  At low load a job then runs
+    with the GPU to itself instead of sharing every round, which lowers the median latency below
+    the back-to-back plain solves (c5 mix at 2 requests/s, srpt_jobs=4: p50 0.23 s against 0.29 s
+    plain and 0.36 s with every job every round), at the cost of the tail: long jobs wait for the
+    short ones (p99 3.9 s against 1.9 s plain and 2.5 s).  0, the default, keeps every round full.
+
     zchunk > 0: 3D jobs that do not set their own and are admitted while at least three others
     are active take z chunks of that many planes (8..32; the lks_desc field of that name).  A lone
     job's chunk is chosen to fill the GPU by itself; in a loaded batch the other jobs fill it, and
@@ -128,7 +141,7 @@ class Server:
     the default only in the FP64 rounding of the per-block partial sums."""
 
     def __init__(self, hbm_budget: int = 0, max_active: int = 32, fill_cells: float = 0.0,
-                 max_wait: int = 64, zchunk: int = 0):
+                 max_wait: int = 64, zchunk: int = 0, srpt_jobs: int = 0):
         free, total = torch.cuda.mem_get_info()
         self.budget = int(hbm_budget) if hbm_budget else int(0.8 * free)
         self.max_active = max_active
@@ -136,6 +149,7 @@ class Server:
         self.max_wait = int(max_wait)
         self.zchunk = int(zchunk)
         self.zchunk_jobs = 4  # jobs sharing the GPU (this one included) from which zchunk applies
+        self.srpt_jobs = int(srpt_jobs)
         self.device = torch.cuda.current_device()
         self.stream = torch.cuda.current_stream().cuda_stream
         self.batch = lks.Batch(self.stream)
@@ -257,7 +271,8 @@ class Server:
                     time.sleep(max(0.0, min(0.01, pending[0][0].arrival - (time.perf_counter() - t0))))
                 continue
             running = [a for a in active if not a.done]
-            chosen = select_round(running, self.fill_cells, self.max_wait)
+            chosen = select_round(running, round_fill(len(running), self.fill_cells, self.srpt_jobs),
+                                  self.max_wait)
             if chosen:
                 flags = self.batch.round([a.solver for a in chosen])
                 self.rounds += 1

@@ -116,6 +116,23 @@ def test_server_shortest_work_first_bitwise():
         assert np.array_equal(a.grad, b.grad), a.rid
 
 
+def test_server_single_shortest_job_rounds_bitwise():
+    """With srpt_jobs set, rounds with few jobs running advance only the shortest one and fuller
+    rounds advance every job; every result is still bitwise the single-job entry points' one."""
+    from paper_2506_23895_amd.server import Request, Server, serve_plain
+    cfgs = jobs()[:3]
+    reqs = [Request(k, 0.0, c, I.gamma_field(c["nd"], c["dim"], 50 + k)) for k, c in enumerate(cfgs)]
+    announce("server single shortest job rounds")
+    srv = Server(srpt_jobs=2)  # three jobs: full rounds until one finishes, then one job per round
+    res = srv.serve(reqs)
+    srv.close()
+    ref = serve_plain(reqs)
+    for a, b in zip(res, ref):
+        assert a.status == b.status == "ok"
+        assert a.J == b.J, (a.rid, a.J, b.J)
+        assert np.array_equal(a.grad, b.grad), a.rid
+
+
 def test_submit_returns_futures_with_the_plain_results():
     """Server.submit: requests handed in while others run resolve to (J, dJ/dgamma, latency),
     bitwise those of the single-job entry points; a job whose state goes non-finite raises."""

@@ -2,7 +2,7 @@
 remaining work first, aged by waiting), and which admitted 3D jobs take the server's z chunk."""
 from dataclasses import dataclass
 
-from paper_2506_23895_amd.server import admitted_cfg, select_round
+from paper_2506_23895_amd.server import admitted_cfg, round_fill, select_round
 
 
 @dataclass
@@ -67,3 +67,11 @@ def test_z_chunk_only_for_3d_jobs_admitted_into_a_loaded_gpu():
     assert admitted_cfg(own, 10, 16, 4) is own             # a request's own choice stands
     assert admitted_cfg(c3, 10, 0, 4) is c3                # zchunk 0: off
     assert admitted_cfg(c3, 0, 16, 1)["zchunk"] == 16      # zchunk_jobs 1: every 3D job
+
+
+def test_single_shortest_job_rounds_at_low_load():
+    assert round_fill(3, 0.0, 4) == 1.0 and round_fill(4, 0.0, 4) == 1.0   # one job per round
+    assert round_fill(5, 0.0, 4) == 0.0 and round_fill(5, 4e6, 4) == 4e6   # the usual rounds
+    assert round_fill(1, 0.0, 0) == 0.0                                     # srpt_jobs 0: off
+    a, b = Job(100, 10), Job(50, 3)
+    assert select_round([a, b], round_fill(2, 0.0, 4), 64) == [b]          # the least work left
