@@ -476,7 +476,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5"])
-    ap.add_argument("--requests", type=int, default=12, help="served leg: number of requests")
+    ap.add_argument("--requests", type=int, default=40, help="served leg: number of requests")
     ap.add_argument("--rate", type=float, default=50.0, help="served leg: arrivals per second")
     ap.add_argument("--rates", default="", help="c5: comma-separated arrival rates to sweep")
     ap.add_argument("--no-served", action="store_true", help="skip the served leg")
