@@ -913,8 +913,8 @@ __device__ __forceinline__ void adj2d_march(const AdjArgs<T> &a, int strip, int 
 // full boundary transpose.  March units come first (they are the longest), then the outer strips'
 // general units, then the y-edge units of the marching strips.  Six rows per march: the launch
 // alone is faster at eight (14.0 against 14.9 us at 1024^2), but the reverse sweep, where the
-// segment recompute shares the GPU, is faster at six (C3 36.7 k -> 36.9 k MLUPS; 4 and 5 rows
-// slower, 10 rows slower).
+// segment recompute shares the GPU, is faster at six (1024^2 D2Q9, 10^4 steps, checkpoint every
+// 100: 36.7 k -> 36.9 k MLUPS; 4, 5 and 10 rows slower).
 #ifndef LKS_ADJ2D_RM
 #define LKS_ADJ2D_RM 6
 #endif
