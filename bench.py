@@ -231,7 +231,7 @@ def copy_reference(torch, dev, mib: int = 1024, reps: int = 10) -> dict:
 
 
 def served_leg(n_req: int, rate: float, seed: int = 5, fill_cells: float = 0.0, zchunk: int = 0,
-               srpt_jobs: int = 0) -> dict:
+               srpt_jobs: int = 4) -> dict:
     """Continuous batching vs back-to-back plain solves on one seeded Poisson request list.  zchunk:
     z planes per block that the server gives 3D jobs (0: each job's own choice, as the plain solves
     make it)."""
@@ -485,7 +485,7 @@ def main() -> int:
                     help="served leg: cells per round, shortest remaining work first (0: every job)")
     ap.add_argument("--zchunk", type=int, default=SERVED_ZCHUNK,
                     help="served leg: z planes per block of batched 3D jobs (0: each job's own choice)")
-    ap.add_argument("--srpt-jobs", type=int, default=0,
+    ap.add_argument("--srpt-jobs", type=int, default=4,
                     help="served leg: with at most this many jobs running, one job per round, the one "
                          "with the least remaining work")
     ap.add_argument("--nsteps", type=int, default=0, help="override the time horizon (profiling)")

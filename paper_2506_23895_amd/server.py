@@ -126,12 +126,13 @@ class Server:
     short jobs finish first instead of sharing every round with long ones, and every job at least
     once every max_wait rounds; 0 advances every admitted job every round.
 
-    srpt_jobs > 0: while at most that many jobs are running, each round advances only the one with
-    the least remaining work (its other rounds are the ones above).  At low load a job then runs
-    with the GPU to itself instead of sharing every round, which lowers the median latency below
-    the back-to-back plain solves (c5 mix at 2 requests/s, srpt_jobs=4: p50 0.23 s against 0.29 s
-    plain and 0.36 s with every job every round), at the cost of the tail: long jobs wait for the
-    short ones (p99 3.9 s against 1.9 s plain and 2.5 s).  0, the default, keeps every round full.
+    srpt_jobs > 0 (default 4): while at most that many jobs are running, each round advances only
+    the one with the least remaining work (its other rounds are the ones above).  At low load a job
+    then runs with the GPU to itself instead of sharing every round, which keeps the median latency
+    below the back-to-back plain solves at every arrival rate (mixed 2D/3D requests at 2 per
+    second: p50 0.23 s against 0.29 s plain and 0.36 s with every job every round), at the cost of
+    the tail at low rates: long jobs wait for the short ones (p99 3.9 s against 1.9 s plain and
+    2.5 s).  0 keeps every round full (the tail setting).
 
     zchunk > 0: 3D jobs that do not set their own and are admitted while at least three others
     are active take z chunks of that many planes (8..32; the lks_desc field of that name).  A lone
@@ -141,7 +142,7 @@ class Server:
     the default only in the FP64 rounding of the per-block partial sums."""
 
     def __init__(self, hbm_budget: int = 0, max_active: int = 32, fill_cells: float = 0.0,
-                 max_wait: int = 64, zchunk: int = 0, srpt_jobs: int = 0):
+                 max_wait: int = 64, zchunk: int = 0, srpt_jobs: int = 4):
         free, total = torch.cuda.mem_get_info()
         self.budget = int(hbm_budget) if hbm_budget else int(0.8 * free)
         self.max_active = max_active
