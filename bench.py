@@ -231,7 +231,7 @@ def copy_reference(torch, dev, mib: int = 1024, reps: int = 10) -> dict:
 
 
 def served_leg(n_req: int, rate: float, seed: int = 5, fill_cells: float = 0.0, zchunk: int = 0,
-               srpt_jobs: int = 4) -> dict:
+               srpt_jobs: int = 4, max_active: int = 128) -> dict:
     """Continuous batching vs back-to-back plain solves on one seeded Poisson request list.  zchunk:
     z planes per block that the server gives 3D jobs (0: each job's own choice, as the plain solves
     make it)."""
@@ -242,13 +242,13 @@ def served_leg(n_req: int, rate: float, seed: int = 5, fill_cells: float = 0.0, 
         t += float(rng.exponential(1.0 / rate))
         cfg = I.served_job(rng)
         reqs.append(Request(k, t, cfg, I.gamma_field(cfg["nd"], cfg["dim"], 100 + k)))
-    srv = Server(fill_cells=fill_cells, zchunk=zchunk, srpt_jobs=srpt_jobs)
+    srv = Server(fill_cells=fill_cells, zchunk=zchunk, srpt_jobs=srpt_jobs, max_active=max_active)
     served = summarize(srv.serve(reqs))
     rounds = srv.rounds
     srv.close()
     plain = summarize(serve_plain(reqs))
     out = {"requests": n_req, "rate_req_per_s": rate, "served": served, "plain": plain,
-           "rounds": rounds, "served_zchunk": zchunk, "srpt_jobs": srpt_jobs,
+           "rounds": rounds, "served_zchunk": zchunk, "srpt_jobs": srpt_jobs, "max_active": max_active,
            "mix": f"{sum(r.cfg['dim'] == 2 for r in reqs)} 2D / {sum(r.cfg['dim'] == 3 for r in reqs)} 3D, "
                   f"{sum(r.cfg['nsteps'] for r in reqs)} steps in total"}
     if served.get("evals_per_s") and plain.get("evals_per_s"):
@@ -485,6 +485,7 @@ def main() -> int:
                     help="served leg: cells per round, shortest remaining work first (0: every job)")
     ap.add_argument("--zchunk", type=int, default=SERVED_ZCHUNK,
                     help="served leg: z planes per block of batched 3D jobs (0: each job's own choice)")
+    ap.add_argument("--max-active", type=int, default=128, help="served leg: jobs admitted at once")
     ap.add_argument("--srpt-jobs", type=int, default=4,
                     help="served leg: with at most this many jobs running, one job per round, the one "
                          "with the least remaining work")
@@ -549,7 +550,7 @@ def main() -> int:
         for rate in [float(v) for v in args.rates.split(",")]:
             print(f"[bench] served sweep: {args.requests} requests at {rate}/s", flush=True)
             sv = served_leg(args.requests, rate, fill_cells=args.fill_cells, zchunk=args.zchunk,
-                            srpt_jobs=args.srpt_jobs)
+                            srpt_jobs=args.srpt_jobs, max_active=args.max_active)
             sweep.append(sv)
             a, b = sv["served"], sv["plain"]
             rows.append(f"{rate:6.1f} {a.get('evals_per_s', 0):8.3f} {a.get('p50_latency_s', 0):7.2f} "
@@ -571,7 +572,7 @@ def main() -> int:
     if args.workload == "c5":
         t0 = time.perf_counter()
         sv = served_leg(args.requests, args.rate, fill_cells=args.fill_cells, zchunk=args.zchunk,
-                        srpt_jobs=args.srpt_jobs)
+                        srpt_jobs=args.srpt_jobs, max_active=args.max_active)
         dt = time.perf_counter() - t0
         print(json.dumps({
             "metric": "sens-evals/s served (continuous batching) + p50/p99 latency",
@@ -622,7 +623,7 @@ def main() -> int:
     if has_adj and not args.no_served:
         print(f"[bench] served leg: {args.requests} requests at {args.rate}/s", flush=True)
         line["served"] = served_leg(args.requests, args.rate, fill_cells=args.fill_cells, zchunk=args.zchunk,
-                        srpt_jobs=args.srpt_jobs)
+                        srpt_jobs=args.srpt_jobs, max_active=args.max_active)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, cfg, gamma)
     print(json.dumps(line), flush=True)

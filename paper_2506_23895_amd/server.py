@@ -141,7 +141,7 @@ class Server:
     a job's dJ/dgamma is bitwise the one of a Solver given the same zchunk, and its J differs from
     the default only in the FP64 rounding of the per-block partial sums."""
 
-    def __init__(self, hbm_budget: int = 0, max_active: int = 32, fill_cells: float = 0.0,
+    def __init__(self, hbm_budget: int = 0, max_active: int = 128, fill_cells: float = 0.0,
                  max_wait: int = 64, zchunk: int = 0, srpt_jobs: int = 4):
         free, total = torch.cuda.mem_get_info()
         self.budget = int(hbm_budget) if hbm_budget else int(0.8 * free)
